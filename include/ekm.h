@@ -1,0 +1,164 @@
+/*
+ * ekm.h - C ABI of the exact, index-accelerated k-means library for AMD
+ * MI355X (gfx950).
+ *
+ * The library computes Lloyd's k-means exactly (problem definition, Eq. (1):
+ * minimise the sum of squared distances to cluster means; Lloyd's
+ * algorithm: assign each point to its nearest centroid, then replace every
+ * centroid by the mean of its points).  Index-based acceleration must give
+ * the same result as Lloyd's algorithm (related-work subsection on accelerated
+ * Lloyd's algorithms); here that is a hard guarantee: every assignment equals
+ * the lowest-index argmin of the canonical FP64 squared distance
+ *     D(x, c) = fl(...fl(fl((x_0-c_0)^2) + fl((x_1-c_1)^2)) + ...)   (no FMA)
+ * and every centroid equals RN(exact sum of its points) / count in IEEE FP64.
+ * An empty cluster keeps its previous centroid.
+ *
+ * Conventions for every entry point:
+ *  - Never throws; returns a km_status.  On failure the reason is available
+ *    from kmeans_last_error() (thread-local, valid until the next call on
+ *    the same thread).  Argument errors are detected before any GPU work.
+ *  - Pointers documented as "device" are HIP device pointers owned by the
+ *    caller; "host" pointers are ordinary host memory owned by the caller.
+ *    The library owns only the workspace inside a km_ctx (allocated by
+ *    kmeans_init, released by kmeans_destroy).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All GPU work is ordered on that stream; device outputs are valid once
+ *    the stream has completed the call's work.  Calls that return host data
+ *    (statistics, iteration counts) synchronise the stream themselves.
+ *  - Point arrays are row-major n x d (d = 2 or 3); centroid arrays are
+ *    row-major k x d FP64.  Assignments are int32 centroid indices 0..k-1 in
+ *    the caller's point order.
+ */
+#ifndef EKM_H
+#define EKM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define EKM_API __attribute__((visibility("default")))
+#else
+#define EKM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KM_OK = 0,
+    KM_ERR_INVALID = 1,     /* bad argument (null pointer, k<1, k>n, d not 2/3, non-finite input ...) */
+    KM_ERR_OOM = 2,         /* device allocation failed or workspace_limit_bytes too small */
+    KM_ERR_HIP = 3,         /* a HIP runtime call failed */
+    KM_ERR_UNSUPPORTED = 4, /* valid but unsupported combination (e.g. FP64 points with KM_INDEXED) */
+    KM_ERR_NOT_EXACT = 5    /* coordinates span too many binary orders of magnitude for the
+                               exact fixed-point centroid sums (see kmeans_init) */
+} km_status;
+
+typedef enum { KM_F64 = 0, KM_F32 = 1 } km_dtype;
+
+typedef enum {
+    KM_BRUTE = 0,   /* every point against every centroid (Lloyd's assignment step) */
+    KM_INDEXED = 1  /* point leaves + centroid tree pruning (the paper's accelerator) */
+} km_algo;
+
+/* flags */
+#define KM_FLAG_SSE 1u  /* also compute the objective sum_i D(x_i, c_in[a(i)]) each step */
+
+typedef struct km_config {
+    int32_t d;           /* point dimension: 2 or 3 */
+    int32_t point_dtype; /* km_dtype of the points passed to kmeans_init */
+    int32_t algo;        /* km_algo.  KM_INDEXED requires KM_F32 points. */
+    int32_t leaf_size;   /* f: maximum points per leaf, 0 = default (64); must be 0 or a
+                            power of two in [8, 64] */
+    int32_t cand_tile;   /* brute path: centroids staged in LDS per tile, 0 = default (1024) */
+    uint32_t flags;      /* KM_FLAG_* */
+    int64_t workspace_limit_bytes; /* 0 = unlimited; otherwise kmeans_init fails with
+                                      KM_ERR_OOM if the workspace would exceed it */
+} km_config;
+
+/* Per-step counters.  A "distance evaluation" is one FP32 (or, on the FP64
+ * brute path, FP64) point-centroid squared distance. */
+typedef struct km_iter_stats {
+    int64_t n_changed;          /* points whose assignment differs from the previous step
+                                   (all n on the first step of a context) */
+    int64_t dist_evals;         /* distance evaluations in the fast pass */
+    int64_t brute_evals;        /* n * k: what Lloyd's assignment step evaluates */
+    int64_t single_cand_points; /* points in leaves with one candidate centroid, assigned
+                                   without computing any distance (Eq. (6)'s batch case) */
+    int64_t rechecked;          /* points whose FP32 margin fell under the error bound and
+                                   were decided by canonical FP64 distances */
+    int64_t cand_total;         /* sum over leaves of candidate-list lengths */
+    double sse;                 /* sum_i D(x_i, c_in[a(i)]) if KM_FLAG_SSE, else 0 */
+} km_iter_stats;
+
+typedef struct km_ctx km_ctx;
+
+/* Device workspace kmeans_init would allocate for this configuration, in
+ * bytes (an upper bound; 0 if the configuration is invalid). */
+EKM_API size_t kmeans_workspace_bytes(const km_config *cfg, int64_t n, int64_t k);
+
+/* Create a context for `n` points and `k` clusters.
+ *   points: device, n x d row-major, FP32 or FP64 per cfg->point_dtype.  Copied
+ *           into the context (reordered along a Morton curve and cut into
+ *           leaves of at most f points; Algorithm 1 builds its point index
+ *           once, before the loop), so the caller may free it afterwards.
+ * Errors: KM_ERR_INVALID for null pointers, k < 1, k > n, n >= 2^31, d not in
+ * {2,3}, non-finite coordinates; KM_ERR_NOT_EXACT when the exact centroid
+ * sums would need more than 94 bits; KM_ERR_OOM; KM_ERR_HIP. */
+EKM_API km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, int64_t n,
+                      int64_t k, void *stream);
+
+/* One Lloyd iteration (Algorithm 1, one pass of its outer loop): build the
+ * centroid tree from c_in, assign every point, refine the centroids.
+ *   c_in:       device, k x d FP64, the centroids to assign against.
+ *   c_out:      device, k x d FP64, receives the refined centroids; may equal c_in.
+ *   assign_out: device, n int32 in caller order, or NULL.
+ *   stats:      host, or NULL.  Non-NULL makes the call synchronise the stream.
+ * Errors: KM_ERR_INVALID (null ctx / c_in / c_out, non-finite c_in values are
+ * not checked), KM_ERR_HIP. */
+EKM_API km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out,
+                      km_iter_stats *stats);
+
+/* Up to max_iter Lloyd iterations starting from c_inout (device, k x d FP64),
+ * which receives the final centroids.  With stop_when_stable != 0 the loop
+ * ends after the first iteration t >= 2 whose assignment equals that of
+ * iteration t-1 (the paper's loop runs until the centroids stop moving; with
+ * exact means the two tests agree).
+ *   assign_out: device, n int32 (caller order) final assignment, or NULL.
+ *   iters_done: host, or NULL.
+ *   per_iter:   host array of max_iter entries, or NULL.
+ * The call synchronises the stream when stop_when_stable, iters_done or
+ * per_iter asks for host data. */
+EKM_API km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t max_iter,
+                     int32_t stop_when_stable, int32_t *iters_done, km_iter_stats *per_iter);
+
+/* Release the context and its workspace (synchronises its stream).  NULL is a no-op. */
+EKM_API km_status kmeans_destroy(km_ctx *ctx);
+
+/* Distortion loss of Eq. (1) for fixed centroids, for B independent clouds.
+ *   x: device, B x n x d (FP32 or FP64 per dtype); c: device, B x k x d, same dtype.
+ *   assign_out: device, B x n int32 (lowest-index nearest centroid, exact as above).
+ *   loss_out:   device, B FP64: sum_i D(x_i, c_a(i)) accumulated in FP64.
+ * Errors: KM_ERR_INVALID (null pointers, sizes < 1, d not 2/3), KM_ERR_HIP. */
+EKM_API km_status distortion_fwd(const void *x, const void *c, int32_t dtype, int64_t B, int64_t n,
+                         int64_t k, int32_t d, int32_t *assign_out, double *loss_out, void *stream);
+
+/* Gradient of sum_b g_b L_b with the assignment held fixed (it is piecewise
+ * constant in x and c):
+ *   grad_x[b,i] = 2 g_b (x_i - c_a(i))
+ *   grad_c[b,j] = 2 g_b sum_{i in S_j} (c_j - x_i)   (accumulated in FP64)
+ *   assign: device, B x n int32 from distortion_fwd; grad_loss: device, B FP64.
+ *   grad_x / grad_c: device, same shape and dtype as x / c, or NULL to skip. */
+EKM_API km_status distortion_bwd(const void *x, const void *c, const int32_t *assign,
+                         const double *grad_loss, int32_t dtype, int64_t B, int64_t n, int64_t k,
+                         int32_t d, void *grad_x, void *grad_c, void *stream);
+
+/* Human-readable reason for the last non-OK status on this thread. */
+EKM_API const char *kmeans_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EKM_H */

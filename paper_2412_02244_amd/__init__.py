@@ -1,0 +1,35 @@
+"""Exact, index-accelerated k-means for AMD MI355X (gfx950).
+
+The computation lives in ``libekm.so`` (hand-written HIP kernels behind the C
+ABI in ``include/ekm.h``); this package only marshals torch tensors to it.
+"""
+
+from ._binding import (  # noqa: F401
+    EXPORTED,
+    KM_BRUTE,
+    KM_ERR_HIP,
+    KM_ERR_INVALID,
+    KM_ERR_NOT_EXACT,
+    KM_ERR_OOM,
+    KM_ERR_UNSUPPORTED,
+    KM_F32,
+    KM_F64,
+    KM_FLAG_SSE,
+    KM_INDEXED,
+    KM_OK,
+    LIB_PATH,
+    Context,
+    Distortion,
+    EKMError,
+    KmConfig,
+    KmIterStats,
+    distortion_bwd,
+    distortion_fwd,
+    kmeans_destroy,
+    kmeans_init,
+    kmeans_last_error,
+    kmeans_run,
+    kmeans_step,
+    kmeans_workspace_bytes,
+    load_library,
+)

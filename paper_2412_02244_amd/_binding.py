@@ -1,0 +1,225 @@
+"""ctypes binding of libekm (include/ekm.h): argument marshalling only.
+
+Every function takes torch tensors that already live on the GPU, passes their
+device pointers and the current HIP stream to the C ABI, and raises
+``EKMError`` with ``kmeans_last_error()`` on a non-OK status.  No step of the
+computation runs here; if the library is missing this module raises instead
+of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libekm.so")
+
+KM_OK, KM_ERR_INVALID, KM_ERR_OOM, KM_ERR_HIP, KM_ERR_UNSUPPORTED, KM_ERR_NOT_EXACT = range(6)
+KM_F64, KM_F32 = 0, 1
+KM_BRUTE, KM_INDEXED = 0, 1
+KM_FLAG_SSE = 1
+
+EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy",
+            "distortion_fwd", "distortion_bwd", "kmeans_last_error")
+
+
+class EKMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ekm status {status}: {msg}")
+        self.status = status
+
+
+class KmConfig(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("point_dtype", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("cand_tile", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("workspace_limit_bytes", ctypes.c_int64)]
+
+
+class KmIterStats(ctypes.Structure):
+    _fields_ = [("n_changed", ctypes.c_int64), ("dist_evals", ctypes.c_int64), ("brute_evals", ctypes.c_int64),
+                ("single_cand_points", ctypes.c_int64), ("rechecked", ctypes.c_int64),
+                ("cand_total", ctypes.c_int64), ("sse", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libekm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2412_02244_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.kmeans_workspace_bytes.argtypes = [ctypes.POINTER(KmConfig), I64, I64]
+    lib.kmeans_workspace_bytes.restype = ctypes.c_size_t
+    lib.kmeans_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KmConfig), P, I64, I64, P]
+    lib.kmeans_step.argtypes = [P, P, P, P, ctypes.POINTER(KmIterStats)]
+    lib.kmeans_run.argtypes = [P, P, P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(KmIterStats)]
+    lib.kmeans_destroy.argtypes = [P]
+    lib.distortion_fwd.argtypes = [P, P, I32, I64, I64, I64, I32, P, P, P]
+    lib.distortion_bwd.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
+    lib.kmeans_last_error.restype = ctypes.c_char_p
+    for name in ("kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy", "distortion_fwd", "distortion_bwd"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def kmeans_last_error() -> str:
+    return load_library().kmeans_last_error().decode()
+
+
+def _check(status: int):
+    if status != KM_OK:
+        raise EKMError(status, kmeans_last_error())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _pt_dtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return KM_F32
+    if t.dtype == torch.float64:
+        return KM_F64
+    raise ValueError(f"points must be float32 or float64, got {t.dtype}")
+
+
+def kmeans_workspace_bytes(n: int, k: int, d: int, point_dtype: int = KM_F32, algo: int = KM_INDEXED,
+                           leaf_size: int = 0, cand_tile: int = 0) -> int:
+    cfg = KmConfig(d, point_dtype, algo, leaf_size, cand_tile, 0, 0)
+    return int(load_library().kmeans_workspace_bytes(ctypes.byref(cfg), n, k))
+
+
+class Context:
+    """Owns a km_ctx; released by ``kmeans_destroy`` (or when collected)."""
+
+    def __init__(self, handle: int, n: int, k: int, d: int):
+        self.handle, self.n, self.k, self.d = handle, n, k, d
+
+    def close(self):
+        if self.handle:
+            _check(load_library().kmeans_destroy(ctypes.c_void_p(self.handle)))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kmeans_init(points: torch.Tensor, k: int, algo: int = KM_INDEXED, leaf_size: int = 0, cand_tile: int = 0,
+                flags: int = 0, workspace_limit_bytes: int = 0) -> Context:
+    """Create a context over ``points`` ([n, d] float32/float64 on the GPU)."""
+    if points.dim() != 2:
+        raise ValueError("points must be [n, d]")
+    n, d = points.shape
+    cfg = KmConfig(d, _pt_dtype(points), algo, leaf_size, cand_tile, flags, workspace_limit_bytes)
+    h = ctypes.c_void_p()
+    _check(load_library().kmeans_init(ctypes.byref(h), ctypes.byref(cfg), _dev(points, "points"), n, k,
+                                      _stream()))
+    return Context(h.value, n, k, d)
+
+
+def kmeans_step(ctx: Context, c_in: torch.Tensor, c_out: torch.Tensor | None = None,
+                assign_out: torch.Tensor | None = None, stats: bool = False):
+    """One Lloyd iteration; returns ``c_out`` (and a stats dict when ``stats``)."""
+    if c_out is None:
+        c_out = torch.empty_like(c_in)
+    st = KmIterStats()
+    _check(load_library().kmeans_step(
+        ctypes.c_void_p(ctx.handle), _dev(c_in, "c_in", torch.float64), _dev(c_out, "c_out", torch.float64),
+        None if assign_out is None else _dev(assign_out, "assign_out", torch.int32),
+        ctypes.byref(st) if stats else None))
+    return (c_out, st.as_dict()) if stats else c_out
+
+
+def kmeans_run(ctx: Context, c_inout: torch.Tensor, max_iter: int, stop_when_stable: bool = False,
+               assign_out: torch.Tensor | None = None, per_iter: bool = False):
+    """Up to ``max_iter`` iterations in place on ``c_inout``; returns (iterations, [stats])."""
+    arr = (KmIterStats * max(1, max_iter))() if per_iter else None
+    it = ctypes.c_int32(0)
+    _check(load_library().kmeans_run(
+        ctypes.c_void_p(ctx.handle), _dev(c_inout, "c_inout", torch.float64),
+        None if assign_out is None else _dev(assign_out, "assign_out", torch.int32),
+        max_iter, int(bool(stop_when_stable)), ctypes.byref(it), arr))
+    stats = [arr[i].as_dict() for i in range(it.value)] if per_iter else None
+    return it.value, stats
+
+
+def kmeans_destroy(ctx: Context):
+    ctx.close()
+
+
+def distortion_fwd(x: torch.Tensor, c: torch.Tensor):
+    """``x [B,n,d]``, ``c [B,k,d]`` -> ``(assign int32 [B,n], loss float64 [B])``."""
+    if x.dim() != 3 or c.dim() != 3 or x.shape[0] != c.shape[0] or x.shape[2] != c.shape[2]:
+        raise ValueError("x must be [B,n,d] and c [B,k,d]")
+    if x.dtype != c.dtype:
+        raise ValueError("x and c must have the same dtype")
+    B, n, d = x.shape
+    k = c.shape[1]
+    a = torch.empty((B, n), dtype=torch.int32, device=x.device)
+    loss = torch.empty(B, dtype=torch.float64, device=x.device)
+    _check(load_library().distortion_fwd(_dev(x, "x"), _dev(c, "c"), _pt_dtype(x), B, n, k, d, a.data_ptr(),
+                                         loss.data_ptr(), _stream()))
+    return a, loss
+
+
+def distortion_bwd(x: torch.Tensor, c: torch.Tensor, assign: torch.Tensor, grad_loss: torch.Tensor,
+                   need_x: bool = True, need_c: bool = True):
+    """Gradients of ``sum_b grad_loss[b] * L_b`` -> ``(grad_x or None, grad_c or None)``."""
+    B, n, d = x.shape
+    k = c.shape[1]
+    gx = torch.empty_like(x) if need_x else None
+    gc = torch.empty_like(c) if need_c else None
+    _check(load_library().distortion_bwd(
+        _dev(x, "x"), _dev(c, "c"), _dev(assign, "assign", torch.int32), _dev(grad_loss, "grad_loss", torch.float64),
+        _pt_dtype(x), B, n, k, d, None if gx is None else gx.data_ptr(), None if gc is None else gc.data_ptr(),
+        _stream()))
+    return gx, gc
+
+
+class Distortion(torch.autograd.Function):
+    """Per-cloud distortion ``L_b = sum_i ||x_i - c_a(i)||^2`` (FP64 values, Eq. (1)).
+
+    ``forward(x [B,n,d], c [B,k,d]) -> loss [B] float64``; the nearest-centroid
+    assignment is saved and held fixed in backward.
+    """
+
+    @staticmethod
+    def forward(ctx, x, c):
+        x = x.contiguous()
+        c = c.contiguous()
+        a, loss = distortion_fwd(x, c)
+        ctx.save_for_backward(x, c, a)
+        ctx.mark_non_differentiable(a)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        x, c, a = ctx.saved_tensors
+        g = grad_loss.to(torch.float64).contiguous()
+        gx, gc = distortion_bwd(x, c, a, g, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return gx, gc

@@ -1,0 +1,320 @@
+// C ABI of libekm: argument checks, workspace, and the per-iteration
+// pipeline  A1 centroid tree -> A2 leaf candidates -> A3/A4 assignment with
+// fused exact accumulation -> A5 refinement (one pass of Algorithm 1's loop).
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "ekm_internal.hpp"
+
+namespace ekm {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+bool hip_ok(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return true;
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+int64_t assign_blocks(const km_ctx *ctx);
+
+static int ceil_log2(int64_t v)
+{
+    int h = 0;
+    while (((int64_t)1 << h) < v)
+        ++h;
+    return h;
+}
+
+static km_status check_config(const km_config *cfg, int64_t n, int64_t k)
+{
+    if (!cfg) {
+        set_error("null km_config");
+        return KM_ERR_INVALID;
+    }
+    if (cfg->d != 2 && cfg->d != 3) {
+        set_error("d must be 2 or 3");
+        return KM_ERR_INVALID;
+    }
+    if (cfg->point_dtype != KM_F32 && cfg->point_dtype != KM_F64) {
+        set_error("point_dtype must be KM_F32 or KM_F64");
+        return KM_ERR_INVALID;
+    }
+    if (cfg->algo != KM_BRUTE && cfg->algo != KM_INDEXED) {
+        set_error("algo must be KM_BRUTE or KM_INDEXED");
+        return KM_ERR_INVALID;
+    }
+    if (n < 1 || n >= ((int64_t)1 << 31)) {
+        set_error("n must be in [1, 2^31)");
+        return KM_ERR_INVALID;
+    }
+    if (k < 1 || k > n) {
+        set_error("k must be in [1, n]");
+        return KM_ERR_INVALID;
+    }
+    if (k > ((int64_t)1 << 20)) {
+        set_error("k must be at most 2^20");
+        return KM_ERR_UNSUPPORTED;
+    }
+    int f = cfg->leaf_size;
+    if (f != 0 && (f < 8 || f > MAX_LEAF || (f & (f - 1)))) {
+        set_error("leaf_size must be 0 or a power of two in [8, 64]");
+        return KM_ERR_INVALID;
+    }
+    int t = cfg->cand_tile;
+    if (t != 0 && (t < 64 || t > 2048)) {
+        set_error("cand_tile must be 0 or in [64, 2048]");
+        return KM_ERR_INVALID;
+    }
+    if (cfg->algo == KM_INDEXED && cfg->point_dtype != KM_F32) {
+        set_error("KM_INDEXED needs FP32 points (FP64 points run with KM_BRUTE)");
+        return KM_ERR_UNSUPPORTED;
+    }
+    return KM_OK;
+}
+
+// Upper bound of the device workspace (leaves bounded by n).
+static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
+{
+    const int d = cfg->d;
+    const size_t es = cfg->point_dtype == KM_F32 ? 4 : 8;
+    size_t b = 0;
+    b += (size_t)n * d * es;              // xs
+    b += (size_t)n * 4 * 5;               // perm, a, keys, keys2, vals2
+    b += radix_scratch_words(n) * 4;      // histogram
+    b += scan_scratch_words(radix_scratch_words(n) > (size_t)n ? radix_scratch_words(n) : n) * 4;
+    int64_t L = n;                        // leaves <= n
+    b += (size_t)(L + 1) * 4;             // leaf_start
+    if (cfg->algo == KM_INDEXED) {
+        b += (size_t)L * (32 + d * 16 + 4 + 4 + 4 * CAND_CAP); // box, sums, prev, ncand, cand
+        int64_t nb = (k + TREE_BUCKET - 1) / TREE_BUCKET;
+        b += ((size_t)1 << (ceil_log2(nb) + 1)) * 32; // node boxes
+        b += (size_t)k * 16;                          // cs
+    }
+    b += (size_t)k * (16 + 4 + d * 16 + 4); // c32, cval, acc, cnt
+    int64_t nblk = cfg->algo == KM_INDEXED ? (L * WAVE + 255) / 256 : (n + 255) / 256;
+    b += (size_t)nblk * (NSTAT * 8 + 8);
+    b += 4096;
+    return b;
+}
+
+static km_status alloc_fail(km_ctx *ctx)
+{
+    (void)ctx;
+    set_error("device allocation failed");
+    return KM_ERR_OOM;
+}
+
+} // namespace ekm
+
+using namespace ekm;
+
+extern "C" {
+
+size_t kmeans_workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
+{
+    if (check_config(cfg, n, k) != KM_OK)
+        return 0;
+    return workspace_bytes(cfg, n, k);
+}
+
+const char *kmeans_last_error(void) { return g_error.c_str(); }
+
+km_status kmeans_destroy(km_ctx *ctx)
+{
+    if (!ctx)
+        return KM_OK;
+    hipStreamSynchronize(ctx->stream);
+    for (void *p : ctx->mem.ptrs)
+        hipFree(p);
+    if (ctx->host_stat)
+        hipHostFree(ctx->host_stat);
+    delete ctx;
+    return KM_OK;
+}
+
+km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, int64_t n, int64_t k, void *stream)
+{
+    if (!out) {
+        set_error("kmeans_init: null output pointer");
+        return KM_ERR_INVALID;
+    }
+    *out = nullptr;
+    km_status s = check_config(cfg, n, k);
+    if (s != KM_OK)
+        return s;
+    if (!points) {
+        set_error("kmeans_init: null points");
+        return KM_ERR_INVALID;
+    }
+    if (cfg->workspace_limit_bytes > 0 && workspace_bytes(cfg, n, k) > (size_t)cfg->workspace_limit_bytes) {
+        set_error("kmeans_init: workspace of " + std::to_string(workspace_bytes(cfg, n, k)) +
+                  " bytes exceeds workspace_limit_bytes");
+        return KM_ERR_OOM;
+    }
+    static std::once_flag once;
+    static hipError_t setup_err = hipSuccess;
+    std::call_once(once, [] { setup_err = tree_setup(); });
+    if (!hip_ok(setup_err, "kmeans_init: kernel setup"))
+        return KM_ERR_HIP;
+
+    km_ctx *ctx = new km_ctx();
+    ctx->cfg = *cfg;
+    ctx->n = n;
+    ctx->k = k;
+    ctx->d = cfg->d;
+    ctx->f = cfg->leaf_size ? cfg->leaf_size : 64;
+    ctx->tile = cfg->cand_tile ? cfg->cand_tile : 1024;
+    ctx->stream = (hipStream_t)stream;
+    hipGetDevice(&ctx->device);
+
+    s = build_leaves(ctx, points);
+    if (s != KM_OK) {
+        kmeans_destroy(ctx);
+        return s;
+    }
+    hipStream_t st = ctx->stream;
+    const int64_t L = ctx->L;
+    ctx->a = ctx_alloc<int32_t>(ctx, n);
+    ctx->c32 = ctx_alloc<float4>(ctx, k);
+    ctx->cval = ctx_alloc<int32_t>(ctx, k);
+    ctx->cerr = ctx_alloc<float>(ctx, 1);
+    ctx->acc = ctx_alloc<int64_t>(ctx, (size_t)k * ctx->d * 2);
+    ctx->cnt = ctx_alloc<int32_t>(ctx, k);
+    ctx->nblk_stat = assign_blocks(ctx);
+    ctx->stat_part = ctx_alloc<int64_t>(ctx, (size_t)ctx->nblk_stat * NSTAT);
+    ctx->sse_part = ctx_alloc<double>(ctx, ctx->nblk_stat);
+    ctx->stat_out = ctx_alloc<int64_t>(ctx, NSTAT);
+    ctx->sse_out = ctx_alloc<double>(ctx, 1);
+    if (!ctx->a || !ctx->c32 || !ctx->cval || !ctx->cerr || !ctx->acc || !ctx->cnt || !ctx->stat_part ||
+        !ctx->sse_part || !ctx->stat_out || !ctx->sse_out) {
+        kmeans_destroy(ctx);
+        return alloc_fail(nullptr);
+    }
+    if (cfg->algo == KM_INDEXED) {
+        int64_t nb = (k + TREE_BUCKET - 1) / TREE_BUCKET;
+        ctx->nbuckets = nb;
+        ctx->tree_h = ceil_log2(nb);
+        ctx->nnodes = (int64_t)2 << ctx->tree_h;
+        ctx->cs = ctx_alloc<float4>(ctx, k);
+        ctx->node_lo = ctx_alloc<float4>(ctx, ctx->nnodes);
+        ctx->node_hi = ctx_alloc<float4>(ctx, ctx->nnodes);
+        ctx->leaf_prev = ctx_alloc<int32_t>(ctx, L);
+        ctx->cand = ctx_alloc<int32_t>(ctx, (size_t)L * CAND_CAP);
+        ctx->ncand = ctx_alloc<int32_t>(ctx, L);
+        if (!ctx->cs || !ctx->node_lo || !ctx->node_hi || !ctx->leaf_prev || !ctx->cand || !ctx->ncand) {
+            kmeans_destroy(ctx);
+            return alloc_fail(nullptr);
+        }
+        if (!hip_ok(hipMemsetAsync(ctx->leaf_prev, 0xff, L * sizeof(int32_t), st), "hipMemsetAsync")) {
+            kmeans_destroy(ctx);
+            return KM_ERR_HIP;
+        }
+    }
+    if (hipHostMalloc((void **)&ctx->host_stat, (NSTAT + 1) * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+        ctx->host_stat = nullptr;
+        kmeans_destroy(ctx);
+        return alloc_fail(nullptr);
+    }
+    bool ok = hip_ok(hipMemsetAsync(ctx->a, 0xff, n * sizeof(int32_t), st), "hipMemsetAsync") &&
+              hip_ok(hipMemsetAsync(ctx->cerr, 0, sizeof(float), st), "hipMemsetAsync") &&
+              hip_ok(hipMemsetAsync(ctx->acc, 0, (size_t)k * ctx->d * 2 * sizeof(int64_t), st), "hipMemsetAsync") &&
+              hip_ok(hipMemsetAsync(ctx->cnt, 0, k * sizeof(int32_t), st), "hipMemsetAsync") &&
+              hip_ok(hipStreamSynchronize(st), "kmeans_init: hipStreamSynchronize");
+    if (!ok) {
+        kmeans_destroy(ctx);
+        return KM_ERR_HIP;
+    }
+    if (cfg->workspace_limit_bytes > 0 && ctx->mem.bytes > (size_t)cfg->workspace_limit_bytes) {
+        size_t used = ctx->mem.bytes;
+        kmeans_destroy(ctx);
+        set_error("kmeans_init: workspace of " + std::to_string(used) + " bytes exceeds workspace_limit_bytes");
+        return KM_ERR_OOM;
+    }
+    *out = ctx;
+    return KM_OK;
+}
+
+km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, km_iter_stats *stats)
+{
+    if (!ctx || !c_in || !c_out) {
+        set_error("kmeans_step: null argument");
+        return KM_ERR_INVALID;
+    }
+    km_status s = KM_OK;
+    if (ctx->cfg.point_dtype == KM_F32) {
+        s = build_centroid_tree(ctx, c_in);
+        if (s != KM_OK)
+            return s;
+    }
+    bool want_sse = (ctx->cfg.flags & KM_FLAG_SSE) != 0;
+    s = run_assign(ctx, c_in, want_sse);
+    if (s != KM_OK)
+        return s;
+    s = run_finalize(ctx, c_in, c_out, assign_out);
+    if (s != KM_OK)
+        return s;
+    ctx->steps_done++;
+    if (stats) {
+        if (!hip_ok(hipMemcpyAsync(ctx->host_stat, ctx->stat_out, NSTAT * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                   ctx->stream),
+                    "kmeans_step: stats copy") ||
+            !hip_ok(hipMemcpyAsync(ctx->host_stat + NSTAT, ctx->sse_out, sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream),
+                    "kmeans_step: stats copy") ||
+            !hip_ok(hipStreamSynchronize(ctx->stream), "kmeans_step: hipStreamSynchronize"))
+            return KM_ERR_HIP;
+        const int64_t *h = ctx->host_stat;
+        stats->n_changed = h[ST_CHANGED];
+        stats->dist_evals = h[ST_EVALS];
+        stats->brute_evals = ctx->n * ctx->k;
+        stats->single_cand_points = h[ST_SINGLE];
+        stats->rechecked = h[ST_RECHECK];
+        stats->cand_total = h[ST_CANDS];
+        double sse;
+        memcpy(&sse, h + NSTAT, sizeof(double));
+        stats->sse = want_sse ? sse : 0.0;
+    }
+    return KM_OK;
+}
+
+km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t max_iter, int32_t stop_when_stable,
+                     int32_t *iters_done, km_iter_stats *per_iter)
+{
+    if (!ctx || !c_inout) {
+        set_error("kmeans_run: null argument");
+        return KM_ERR_INVALID;
+    }
+    if (max_iter < 0) {
+        set_error("kmeans_run: max_iter must be >= 0");
+        return KM_ERR_INVALID;
+    }
+    int t = 0;
+    for (; t < max_iter; ++t) {
+        km_iter_stats tmp;
+        km_iter_stats *sp = per_iter ? &per_iter[t] : (stop_when_stable ? &tmp : nullptr);
+        km_status s = kmeans_step(ctx, c_inout, c_inout, nullptr, sp);
+        if (s != KM_OK)
+            return s;
+        if (stop_when_stable && t >= 1 && sp->n_changed == 0) {
+            ++t;
+            break;
+        }
+    }
+    if (assign_out && ctx->steps_done > 0) {
+        km_status s = scatter_assignment(ctx, assign_out);
+        if (s != KM_OK)
+            return s;
+    }
+    if (iters_done)
+        *iters_done = t;
+    return KM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,340 @@
+// Distortion loss of Eq. (1) for fixed centroids and its gradient, for a
+// batch of B independent clouds.
+//
+//   L_b = sum_i D(x_i, c_a(i)),  a(i) = lowest-index nearest centroid
+//   dL/dx_i = 2 (x_i - c_a(i)),  dL/dc_j = 2 sum_{i in S_j} (c_j - x_i)
+// The assignment is piecewise constant, so it carries no gradient.
+//
+// Forward: one thread per point scans its cloud's centroids from LDS in FP32
+// (FP32 centroids are used as given, so the only error is the distance
+// evaluation) and re-decides near ties with canonical FP64 distances; the
+// loss is an FP64 sum in a fixed order.  Backward: grad_x is elementwise in
+// FP64; grad_c uses exact fixed-point cluster sums (integer atomics), so
+// RN(cnt_j c_j - sum x_i) is computed once from the exact value.
+#include "ekm_internal.hpp"
+
+namespace ekm {
+
+constexpr int DT_THREADS = 256;
+constexpr int DT_TILE = 1024;
+
+template <class T, int D>
+__global__ void __launch_bounds__(DT_THREADS) k_dist_assign(const T *x, const T *c, int64_t n, int64_t k, int32_t *a)
+{
+    __shared__ float4 tile[DT_TILE];
+    const int64_t b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = p < n;
+    const T *xb = x + b * n * D, *cb = c + b * k * D;
+    double xd[D];
+    float xf[D];
+    for (int i = 0; i < D; ++i) {
+        xd[i] = valid ? (double)xb[p * D + i] : 0.0;
+        xf[i] = (float)xd[i];
+    }
+    int best = 0;
+    if (sizeof(T) == 4) {
+        float s1 = INFINITY, s2 = INFINITY;
+        int id1 = 0;
+        for (int64_t t0 = 0; t0 < k; t0 += DT_TILE) {
+            int tn = (int)((k - t0) < DT_TILE ? (k - t0) : DT_TILE);
+            __syncthreads();
+            for (int t = threadIdx.x; t < tn; t += blockDim.x) {
+                float q[3] = {0.0f, 0.0f, 0.0f};
+                for (int i = 0; i < D; ++i)
+                    q[i] = (float)cb[(t0 + t) * D + i];
+                tile[t] = make_float4(q[0], q[1], q[2], 0.0f);
+            }
+            __syncthreads();
+            for (int t = 0; t < tn; ++t) {
+                float4 c4 = tile[t];
+                float cc[3] = {c4.x, c4.y, c4.z};
+                float sv = sqdist32<D>(xf, cc);
+                if (sv < s1) {
+                    s2 = s1;
+                    s1 = sv;
+                    id1 = (int)(t0 + t);
+                } else {
+                    s2 = fminf(s2, sv);
+                }
+            }
+        }
+        best = id1;
+        if (valid && !margin_safe(s1, s2, 0.0f)) {
+            double bd = INFINITY;
+            for (int64_t j = 0; j < k; ++j) {
+                double cd[D];
+                for (int i = 0; i < D; ++i)
+                    cd[i] = (double)cb[j * D + i];
+                double Dv = sqdist64<D>(xd, cd);
+                if (Dv < bd) {
+                    bd = Dv;
+                    best = (int)j;
+                }
+            }
+        }
+    } else {
+        double bd = INFINITY;
+        for (int64_t j = 0; j < k; ++j) {
+            double cd[D];
+            for (int i = 0; i < D; ++i)
+                cd[i] = (double)cb[j * D + i];
+            double Dv = sqdist64<D>(xd, cd);
+            if (Dv < bd) {
+                bd = Dv;
+                best = (int)j;
+            }
+        }
+    }
+    if (valid)
+        a[b * n + p] = best;
+}
+
+// One block per cloud, fixed summation order.
+template <class T, int D>
+__global__ void __launch_bounds__(DT_THREADS) k_dist_loss(const T *x, const T *c, const int32_t *a, int64_t n,
+                                                          int64_t k, double *loss)
+{
+    __shared__ double red[DT_THREADS];
+    const int64_t b = blockIdx.x;
+    const T *xb = x + b * n * D, *cb = c + b * k * D;
+    double s = 0.0;
+    for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
+        int j = a[b * n + p];
+        double xd[D], cd[D];
+        for (int i = 0; i < D; ++i) {
+            xd[i] = (double)xb[p * D + i];
+            cd[i] = (double)cb[(int64_t)j * D + i];
+        }
+        s += sqdist64<D>(xd, cd);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = DT_THREADS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        loss[b] = red[0];
+}
+
+template <class T, int D>
+__global__ void __launch_bounds__(DT_THREADS) k_dist_gx(const T *x, const T *c, const int32_t *a, const double *g,
+                                                        int64_t B, int64_t n, int64_t k, T *gx)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= B * n)
+        return;
+    int64_t b = q / n;
+    int j = a[q];
+    double two_g = 2.0 * g[b];
+    for (int i = 0; i < D; ++i) {
+        double t = (double)x[q * D + i] - (double)c[(b * k + j) * D + i];
+        gx[q * D + i] = (T)(two_g * t);
+    }
+}
+
+struct WinOut {
+    int32_t neg_elsb, emsb, any;
+};
+
+template <class T>
+__global__ void __launch_bounds__(DT_THREADS) k_dist_window(const T *v, int64_t m, WinOut *out)
+{
+    int ne = -100000, em = -100000, any = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x) {
+        T t = v[q];
+        if (t != (T)0) {
+            int el, eh;
+            if (sizeof(T) == 4)
+                bits_f32((float)t, el, eh);
+            else
+                bits_f64((double)t, el, eh);
+            ne = max(ne, -el);
+            em = max(em, eh);
+            any = 1;
+        }
+    }
+    if (any) {
+        atomicMax(&out->neg_elsb, ne);
+        atomicMax(&out->emsb, em);
+        atomicOr(&out->any, 1);
+    }
+}
+
+template <class T, int D>
+__global__ void __launch_bounds__(DT_THREADS) k_dist_acc(const T *x, const int32_t *a, int64_t n, int64_t k, int S,
+                                                         int64_t *acc, int32_t *cnt)
+{
+    const int64_t b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = p < n;
+    int j = valid ? a[b * n + p] : 0;
+    int64_t hi[D], lo[D];
+    for (int i = 0; i < D; ++i) {
+        T v = valid ? x[(b * n + p) * D + i] : (T)0;
+        if (sizeof(T) == 4)
+            fix_split_f32((float)v, S, hi[i], lo[i]);
+        else
+            fix_split_f64((double)v, S, hi[i], lo[i]);
+    }
+    wave_accumulate<D>(valid, j, hi, lo, acc + b * k * D * 2, cnt + b * k);
+}
+
+template <class T, int D>
+__global__ void __launch_bounds__(DT_THREADS) k_dist_gc(const T *c, const double *g, int64_t B, int64_t k, int S,
+                                                        const int64_t *acc, const int32_t *cnt, T *gc)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= B * k)
+        return;
+    int64_t b = q / k;
+    double two_g = 2.0 * g[b];
+    int32_t m = cnt[q];
+    for (int i = 0; i < D; ++i) {
+        int64_t ch, cl;
+        T cv = c[q * D + i];
+        if (sizeof(T) == 4)
+            fix_split_f32((float)cv, S, ch, cl);
+        else
+            fix_split_f64((double)cv, S, ch, cl);
+        __int128 Vc = ((__int128)ch << 32) + (__int128)cl;
+        __int128 Vs = ((__int128)acc[(q * D + i) * 2] << 32) + (__int128)acc[(q * D + i) * 2 + 1];
+        double diff = fix128_to_double(Vc * (__int128)m - Vs, S); // RN(cnt c_j - sum x_i)
+        gc[q * D + i] = (T)(two_g * diff);
+    }
+}
+
+static bool dist_args_ok(const void *x, const void *c, int32_t dtype, int64_t B, int64_t n, int64_t k, int32_t d)
+{
+    if (!x || !c) {
+        set_error("distortion: null pointer");
+        return false;
+    }
+    if (dtype != KM_F32 && dtype != KM_F64) {
+        set_error("distortion: dtype must be KM_F32 or KM_F64");
+        return false;
+    }
+    if (B < 1 || n < 1 || k < 1 || (d != 2 && d != 3)) {
+        set_error("distortion: need B, n, k >= 1 and d in {2, 3}");
+        return false;
+    }
+    if (B > 65535 || n >= ((int64_t)1 << 31) || k >= ((int64_t)1 << 31)) {
+        set_error("distortion: B <= 65535 and n, k < 2^31 required");
+        return false;
+    }
+    return true;
+}
+
+template <class T, int D>
+static km_status fwd_t(const T *x, const T *c, int64_t B, int64_t n, int64_t k, int32_t *a, double *loss,
+                       hipStream_t st)
+{
+    dim3 grid((unsigned)((n + DT_THREADS - 1) / DT_THREADS), (unsigned)B);
+    hipLaunchKernelGGL((k_dist_assign<T, D>), grid, dim3(DT_THREADS), 0, st, x, c, n, k, a);
+    hipLaunchKernelGGL((k_dist_loss<T, D>), dim3((unsigned)B), dim3(DT_THREADS), 0, st, x, c, a, n, k, loss);
+    return hip_ok(hipGetLastError(), "distortion_fwd launch") ? KM_OK : KM_ERR_HIP;
+}
+
+template <class T, int D>
+static km_status bwd_t(const T *x, const T *c, const int32_t *a, const double *g, int64_t B, int64_t n, int64_t k,
+                       T *gx, T *gc, hipStream_t st)
+{
+    if (gx) {
+        int64_t tot = B * n;
+        hipLaunchKernelGGL((k_dist_gx<T, D>), dim3((unsigned)((tot + DT_THREADS - 1) / DT_THREADS)), dim3(DT_THREADS),
+                           0, st, x, c, a, g, B, n, k, gx);
+        if (!hip_ok(hipGetLastError(), "distortion_bwd launch"))
+            return KM_ERR_HIP;
+    }
+    if (!gc)
+        return KM_OK;
+    // exact-sum window over x and c (one small host round trip)
+    size_t acc_bytes = (size_t)B * k * D * 2 * sizeof(int64_t), cnt_bytes = (size_t)B * k * sizeof(int32_t);
+    char *buf = nullptr;
+    if (!hip_ok(hipMallocAsync((void **)&buf, acc_bytes + cnt_bytes + 256, st), "distortion_bwd: hipMallocAsync"))
+        return KM_ERR_OOM;
+    int64_t *acc = (int64_t *)buf;
+    int32_t *cnt = (int32_t *)(buf + acc_bytes);
+    WinOut *win = (WinOut *)(buf + acc_bytes + cnt_bytes + 128 - ((acc_bytes + cnt_bytes) % 128));
+    WinOut h = {-100000, -100000, 0};
+    km_status status = KM_OK;
+    if (!hip_ok(hipMemcpyAsync(win, &h, sizeof(h), hipMemcpyHostToDevice, st), "distortion_bwd: copy") ||
+        !hip_ok(hipMemsetAsync(buf, 0, acc_bytes + cnt_bytes, st), "distortion_bwd: memset"))
+        status = KM_ERR_HIP;
+    if (status == KM_OK) {
+        hipLaunchKernelGGL(k_dist_window<T>, dim3(1024), dim3(DT_THREADS), 0, st, x, B * n * D, win);
+        hipLaunchKernelGGL(k_dist_window<T>, dim3(256), dim3(DT_THREADS), 0, st, c, B * k * D, win);
+        if (!hip_ok(hipMemcpyAsync(&h, win, sizeof(h), hipMemcpyDeviceToHost, st), "distortion_bwd: copy") ||
+            !hip_ok(hipStreamSynchronize(st), "distortion_bwd: sync"))
+            status = KM_ERR_HIP;
+    }
+    if (status == KM_OK) {
+        int S = h.any ? h.neg_elsb : 0;
+        int logn = 0;
+        while (((int64_t)1 << logn) < n)
+            ++logn;
+        // sums need emsb+1+S+log2(n) bits; the product cnt * c_j adds 31 bits
+        if (h.any && (h.emsb + 1 + S + logn > MAX_FIX_BITS || h.emsb + 1 + S + 31 > 125)) {
+            set_error("distortion_bwd: coordinates span too many bits for exact centroid sums");
+            status = KM_ERR_NOT_EXACT;
+        } else {
+            dim3 grid((unsigned)((n + DT_THREADS - 1) / DT_THREADS), (unsigned)B);
+            hipLaunchKernelGGL((k_dist_acc<T, D>), grid, dim3(DT_THREADS), 0, st, x, a, n, k, S, acc, cnt);
+            int64_t tot = B * k;
+            hipLaunchKernelGGL((k_dist_gc<T, D>), dim3((unsigned)((tot + DT_THREADS - 1) / DT_THREADS)),
+                               dim3(DT_THREADS), 0, st, c, g, B, k, S, acc, cnt, gc);
+            if (!hip_ok(hipGetLastError(), "distortion_bwd launch"))
+                status = KM_ERR_HIP;
+        }
+    }
+    hipFreeAsync(buf, st);
+    return status;
+}
+
+} // namespace ekm
+
+using namespace ekm;
+
+extern "C" {
+
+km_status distortion_fwd(const void *x, const void *c, int32_t dtype, int64_t B, int64_t n, int64_t k, int32_t d,
+                         int32_t *assign_out, double *loss_out, void *stream)
+{
+    if (!dist_args_ok(x, c, dtype, B, n, k, d))
+        return KM_ERR_INVALID;
+    if (!assign_out || !loss_out) {
+        set_error("distortion_fwd: null output");
+        return KM_ERR_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == KM_F32)
+        return d == 2 ? fwd_t<float, 2>((const float *)x, (const float *)c, B, n, k, assign_out, loss_out, st)
+                      : fwd_t<float, 3>((const float *)x, (const float *)c, B, n, k, assign_out, loss_out, st);
+    return d == 2 ? fwd_t<double, 2>((const double *)x, (const double *)c, B, n, k, assign_out, loss_out, st)
+                  : fwd_t<double, 3>((const double *)x, (const double *)c, B, n, k, assign_out, loss_out, st);
+}
+
+km_status distortion_bwd(const void *x, const void *c, const int32_t *assign, const double *grad_loss, int32_t dtype,
+                         int64_t B, int64_t n, int64_t k, int32_t d, void *grad_x, void *grad_c, void *stream)
+{
+    if (!dist_args_ok(x, c, dtype, B, n, k, d))
+        return KM_ERR_INVALID;
+    if (!assign || !grad_loss) {
+        set_error("distortion_bwd: null assignment or grad_loss");
+        return KM_ERR_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == KM_F32)
+        return d == 2 ? bwd_t<float, 2>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
+                                        (float *)grad_x, (float *)grad_c, st)
+                      : bwd_t<float, 3>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
+                                        (float *)grad_x, (float *)grad_c, st);
+    return d == 2 ? bwd_t<double, 2>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
+                                     (double *)grad_x, (double *)grad_c, st)
+                  : bwd_t<double, 3>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
+                                     (double *)grad_x, (double *)grad_c, st);
+}
+
+} // extern "C"

@@ -1,0 +1,475 @@
+// Internal declarations shared by the HIP translation units of libekm.
+// Device helpers: Morton codes, conservative FP32 error bounds, exact
+// fixed-point decomposition of coordinates, wave-level reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ekm.h"
+
+namespace ekm {
+
+constexpr int WAVE = 64;
+constexpr int MAX_LEAF = 64;   // a leaf fits one wave
+constexpr int CAND_CAP = 64;   // candidate slots per leaf: one per lane
+constexpr int TREE_BUCKET = 8; // centroids per centroid-tree leaf bucket
+constexpr int NSTAT = 8;       // per-block statistics slots (see StatSlot)
+constexpr int MAX_FIX_BITS = 94;
+
+enum StatSlot {
+    ST_CHANGED = 0,
+    ST_EVALS = 1,
+    ST_SINGLE = 2,
+    ST_RECHECK = 3,
+    ST_CANDS = 4,
+    ST_OVERFLOW_PTS = 5,
+};
+
+// ------------------------------------------------------------------------
+// Morton codes on a 2^b grid per dimension over the data bounding box.
+// 2D: 16 bits per dimension (32-bit key); 3D: 10 bits per dimension (30-bit).
+// ------------------------------------------------------------------------
+__host__ __device__ inline uint32_t spread2(uint32_t v)
+{
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+__host__ __device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+inline constexpr int morton_bits(int d) { return d == 2 ? 16 : 10; }
+inline constexpr int key_bits(int d) { return d == 2 ? 32 : 30; }
+
+struct Grid {
+    float lo[3];
+    float scale[3]; // cells per unit length
+};
+
+__device__ inline uint32_t quantize(float v, float lo, float scale, int bits)
+{
+    float q = floorf((v - lo) * scale);
+    float top = (float)((1u << bits) - 1u);
+    q = fminf(fmaxf(q, 0.0f), top); // NaN-free inputs only
+    return (uint32_t)q;
+}
+
+template <int D>
+__device__ inline uint32_t morton_key(const float *p, const Grid &g)
+{
+    if (D == 2)
+        return spread2(quantize(p[0], g.lo[0], g.scale[0], 16)) |
+               (spread2(quantize(p[1], g.lo[1], g.scale[1], 16)) << 1);
+    return spread3(quantize(p[0], g.lo[0], g.scale[0], 10)) |
+           (spread3(quantize(p[1], g.lo[1], g.scale[1], 10)) << 1) |
+           (spread3(quantize(p[2], g.lo[2], g.scale[2], 10)) << 2);
+}
+
+// ------------------------------------------------------------------------
+// Conservative FP32 decisions.
+//
+// For an FP32 point x and an FP64 centroid c with c' = fl32(c):
+//   D' = exact sum (x_i - c'_i)^2,  s = FP32 evaluation of D' (<= d+2
+//   roundings per term, so |s - D'| <= gamma D' + tau with gamma ~ (d+2)u,
+//   tau covering underflow),  |sqrt(D') - sqrt(D)| <= ||c - c'|| <= e,
+//   and the canonical FP64 D64 is within (d+2)w of the exact D.
+// All these relative errors are far below MARGIN = 2^-16, which also covers
+// the FP32 sqrt and the few roundings of the tests themselves.
+// ------------------------------------------------------------------------
+constexpr float MARGIN_UP = 1.0f + 0x1p-16f;
+constexpr float MARGIN_DN = 1.0f - 0x1p-16f;
+constexpr float TAU = 0x1p-120f;
+
+// Upper bound on sqrt(D64) given FP32 s (of the centroid that will be chosen).
+__device__ inline float dist_hi(float s, float e) { return sqrtf(s + TAU) * MARGIN_UP + e; }
+// Lower bound on sqrt(D64) given FP32 s.
+__device__ inline float dist_lo(float s, float e) { return sqrtf(fmaxf(s - TAU, 0.0f)) * MARGIN_DN - e; }
+
+// True when the FP32 best (s1) is certainly the FP64 argmin against every
+// centroid whose FP32 value is >= s2.
+__device__ inline bool margin_safe(float s1, float s2, float e) { return dist_lo(s2, e) > dist_hi(s1, e); }
+
+// Pruning threshold on FP32 squared box distances.  With U = an FP32
+// max-distance from the box to some existing centroid, any centroid whose
+// FP32 min-distance to the box exceeds prune_threshold(U, e) is strictly
+// farther (in FP64) than that centroid from every point of the box.
+__device__ inline float prune_threshold(float U, float e)
+{
+    float r = (sqrtf(U + TAU) * MARGIN_UP + 2.0f * e) * MARGIN_UP * MARGIN_UP;
+    return r * r * MARGIN_UP + TAU;
+}
+
+template <int D>
+__device__ inline float sqdist32(const float *x, const float *c)
+{
+    float t = x[0] - c[0];
+    float s = t * t;
+#pragma unroll
+    for (int i = 1; i < D; ++i) {
+        t = x[i] - c[i];
+        s = fmaf(t, t, s);
+    }
+    return s;
+}
+
+// Canonical FP64 squared distance: rounded differences, rounded squares,
+// left-to-right sum, no contraction (this library is built with
+// -ffp-contract=off, and the pragma pins it here as well).
+template <int D>
+__device__ inline double sqdist64(const double *x, const double *c)
+{
+#pragma clang fp contract(off)
+    double t = x[0] - c[0];
+    double s = t * t;
+#pragma unroll
+    for (int i = 1; i < D; ++i) {
+        t = x[i] - c[i];
+        s = s + t * t;
+    }
+    return s;
+}
+
+// Box distances (FP32).  lo/hi: leaf box; c: point.
+template <int D>
+__device__ inline float box_mind(const float *lo, const float *hi, const float *c)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float g = fmaxf(fmaxf(lo[i] - c[i], c[i] - hi[i]), 0.0f);
+        s = fmaf(g, g, s);
+    }
+    return s;
+}
+template <int D>
+__device__ inline float box_maxd(const float *lo, const float *hi, const float *c)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float g = fmaxf(fabsf(c[i] - lo[i]), fabsf(hi[i] - c[i]));
+        s = fmaf(g, g, s);
+    }
+    return s;
+}
+// Box-to-box: min and max over point pairs.
+template <int D>
+__device__ inline float bb_mind(const float *alo, const float *ahi, const float *blo, const float *bhi)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float g = fmaxf(fmaxf(alo[i] - bhi[i], blo[i] - ahi[i]), 0.0f);
+        s = fmaf(g, g, s);
+    }
+    return s;
+}
+template <int D>
+__device__ inline float bb_maxd(const float *alo, const float *ahi, const float *blo, const float *bhi)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float g = fmaxf(fabsf(bhi[i] - alo[i]), fabsf(ahi[i] - blo[i]));
+        s = fmaf(g, g, s);
+    }
+    return s;
+}
+
+// ------------------------------------------------------------------------
+// Exact fixed-point coordinates.  Every coordinate v of the data set is an
+// integer multiple of 2^-S (S fixed at init), so V = v * 2^S is an integer
+// of at most MAX_FIX_BITS bits including the sum over all points.  V is kept
+// as hi * 2^32 + lo with lo in [0, 2^32): sums of lo fit int64 for n < 2^31,
+// sums of hi fit int64 because the total stays below 2^94.
+// ------------------------------------------------------------------------
+__device__ inline void fix_split_f32(float v, int S, int64_t &hi, int64_t &lo)
+{
+    uint32_t b = __float_as_uint(v);
+    uint32_t ex = (b >> 23) & 0xffu;
+    int64_t m = (int64_t)(b & 0x7fffffu);
+    int e2;
+    if (ex == 0) {
+        e2 = -149;
+    } else {
+        m |= 0x800000;
+        e2 = (int)ex - 150;
+    }
+    int sh = e2 + S;
+    // sh < 0 only for values whose trailing mantissa zeros make the right
+    // shift exact (S is chosen from each value's lowest set bit).
+    unsigned __int128 mag = sh >= 0 ? ((unsigned __int128)(uint64_t)m << sh)
+                                    : (unsigned __int128)(-sh >= 64 ? 0ull : ((uint64_t)m >> (-sh)));
+    __int128 V = (b >> 31) ? -(__int128)mag : (__int128)mag;
+    hi = (int64_t)(V >> 32);
+    lo = (int64_t)(uint32_t)(uint64_t)V;
+}
+
+__device__ inline void fix_split_f64(double v, int S, int64_t &hi, int64_t &lo)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    uint32_t ex = (uint32_t)((b >> 52) & 0x7ffu);
+    int64_t m = (int64_t)(b & 0xfffffffffffffull);
+    int e2;
+    if (ex == 0) {
+        e2 = -1074;
+    } else {
+        m |= (int64_t)1 << 52;
+        e2 = (int)ex - 1075;
+    }
+    int sh = e2 + S;
+    // sh < 0 only for values whose trailing mantissa zeros make the right
+    // shift exact (S is chosen from each value's lowest set bit).
+    unsigned __int128 mag = sh >= 0 ? ((unsigned __int128)(uint64_t)m << sh)
+                                    : (unsigned __int128)(-sh >= 64 ? 0ull : ((uint64_t)m >> (-sh)));
+    __int128 V = (b >> 63) ? -(__int128)mag : (__int128)mag;
+    hi = (int64_t)(V >> 32);
+    lo = (int64_t)(uint32_t)(uint64_t)V;
+}
+
+// Exponents of the lowest and highest set bit of a nonzero value.
+__device__ inline void bits_f32(float v, int &elsb, int &emsb)
+{
+    uint32_t b = __float_as_uint(v);
+    uint32_t ex = (b >> 23) & 0xffu;
+    uint32_t m = b & 0x7fffffu;
+    int e2 = ex == 0 ? -149 : (int)ex - 150;
+    if (ex)
+        m |= 0x800000u;
+    elsb = e2 + __ffs((int)m) - 1;
+    emsb = e2 + 31 - __clz((int)m);
+}
+__device__ inline void bits_f64(double v, int &elsb, int &emsb)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    uint32_t ex = (uint32_t)((b >> 52) & 0x7ffu);
+    uint64_t m = b & 0xfffffffffffffull;
+    int e2 = ex == 0 ? -1074 : (int)ex - 1075;
+    if (ex)
+        m |= 1ull << 52;
+    elsb = e2 + __ffsll((unsigned long long)m) - 1;
+    emsb = e2 + 63 - __clzll((long long)m);
+}
+
+// Round hi*2^32 + lo (exact integer) times 2^-S to the nearest double, ties to even.
+__device__ inline double fix128_to_double(__int128 V, int S)
+{
+    if (V == 0)
+        return 0.0;
+    bool neg = V < 0;
+    unsigned __int128 M = neg ? (unsigned __int128)(-V) : (unsigned __int128)V;
+    uint64_t mh = (uint64_t)(M >> 64), ml = (uint64_t)M;
+    int top = mh ? 127 - __clzll((long long)mh) : 63 - __clzll((long long)ml); // index of the highest set bit
+    uint64_t mant;
+    int ex; // value = mant * 2^ex * 2^-S
+    if (top <= 52) {
+        mant = ml;
+        ex = 0;
+    } else {
+        int drop = top - 52;
+        unsigned __int128 q = M >> drop;
+        mant = (uint64_t)q;
+        unsigned __int128 rem = M - (q << drop);
+        unsigned __int128 half = (unsigned __int128)1 << (drop - 1);
+        if (rem > half || (rem == half && (mant & 1u))) {
+            ++mant;
+            if (mant == ((uint64_t)1 << 53)) {
+                mant >>= 1;
+                ++drop;
+            }
+        }
+        ex = drop;
+    }
+    double r = ldexp((double)mant, ex - S); // exact: mant < 2^53, no underflow for S < 1000
+    return neg ? -r : r;
+}
+
+__device__ inline double fix_to_double(int64_t hi, int64_t lo, int S)
+{
+    return fix128_to_double(((__int128)hi << 32) + (__int128)lo, S);
+}
+
+// ------------------------------------------------------------------------
+// Wave helpers
+// ------------------------------------------------------------------------
+__device__ inline int lane_id() { return (int)__lane_id(); }
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ inline int64_t wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline int32_t wave_sum_i32(int32_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline float wave_min_f32(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Exact per-cluster accumulation of one wave's points.  Lanes with valid set
+// contribute (count 1, fixed-point coordinates) to cluster `a`.  Lanes of
+// the same cluster are summed in-wave, then one lane adds the partial sums
+// to the global accumulators with integer atomics (order-independent).
+//   acc: [k][D][2] int64 (hi, lo); cnt: [k] int32
+template <int D>
+__device__ inline void wave_accumulate(bool valid, int a, const int64_t (&hi)[D], const int64_t (&lo)[D],
+                                       int64_t *acc, int32_t *cnt)
+{
+    uint64_t active = __ballot(valid);
+    while (active) {
+        int leader = __ffsll((unsigned long long)active) - 1;
+        int c = __shfl(a, leader);
+        bool in = valid && a == c && ((active >> lane_id()) & 1ull);
+        uint64_t grp = __ballot(in);
+        int32_t n = __popcll(grp);
+        int64_t sh[D], sl[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            sh[i] = wave_sum_i64(in ? hi[i] : 0);
+            sl[i] = wave_sum_i64(in ? lo[i] : 0);
+        }
+        if (lane_id() == leader) {
+            int64_t *ac = acc + (int64_t)c * D * 2;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                atomicAdd((unsigned long long *)&ac[2 * i], (unsigned long long)sh[i]);
+                atomicAdd((unsigned long long *)&ac[2 * i + 1], (unsigned long long)sl[i]);
+            }
+            atomicAdd(&cnt[c], n);
+        }
+        active &= ~grp;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Context
+// ------------------------------------------------------------------------
+struct Scratch {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+};
+
+} // namespace ekm
+
+struct km_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    km_config cfg{};
+    int64_t n = 0, k = 0;
+    int d = 2;
+    int f = 64;          // maximum leaf size
+    int tile = 1024;     // brute-path LDS tile (centroids)
+    int S = 0;           // fixed-point scale exponent
+    ekm::Grid grid{};    // Morton grid over the data bounding box
+    // A0: Morton-ordered points and leaves
+    void *xs = nullptr;           // [d][n] float or double
+    int32_t *perm = nullptr;      // [n] Morton position -> caller index
+    int32_t *a = nullptr;         // [n] current assignment in Morton order (-1 before the first step)
+    int64_t L = 0;                // number of leaves
+    int32_t *leaf_start = nullptr;// [L+1]
+    float *leaf_box = nullptr;    // [L][2][4] lo xyz pad, hi xyz pad
+    int64_t *leaf_sum = nullptr;  // [L][d][2] exact fixed-point sums
+    int32_t *leaf_prev = nullptr; // [L] whole-leaf cluster of the previous step, or -1
+    // A1: centroid tree
+    float4 *c32 = nullptr;        // [k] fl32(c) in caller order
+    uint32_t *ckey = nullptr, *ckey2 = nullptr;
+    int32_t *cval = nullptr, *cval2 = nullptr;
+    float4 *cs = nullptr;         // [k] fl32 centroids in tree order (w = id as int bits)
+    int tree_h = 0;               // leaf level of the implicit binary tree
+    int64_t nbuckets = 0, nnodes = 0;
+    float4 *node_lo = nullptr, *node_hi = nullptr; // [nnodes]
+    float *cerr = nullptr;        // [1] bound on ||c - fl32(c)||
+    // A2: candidates
+    int32_t *cand = nullptr;      // [L][CAND_CAP]
+    int32_t *ncand = nullptr;     // [L]  (> CAND_CAP means overflow)
+    // A5: exact sums
+    int64_t *acc = nullptr;       // [k][d][2]
+    int32_t *cnt = nullptr;       // [k]
+    int64_t nblk_stat = 0;
+    int64_t *stat_part = nullptr; // [nblk][NSTAT]
+    double *sse_part = nullptr;   // [nblk]
+    int64_t *stat_out = nullptr;  // [NSTAT]
+    double *sse_out = nullptr;    // [1]
+    int64_t *host_stat = nullptr; // pinned [NSTAT + 1]
+    // radix sort scratch
+    uint32_t *rs_hist = nullptr;
+    int64_t rs_hist_len = 0;
+    uint32_t *scan_tmp = nullptr;
+    ekm::Scratch mem;
+    int steps_done = 0;
+};
+
+namespace ekm {
+
+void set_error(const std::string &msg);
+bool hip_ok(hipError_t e, const char *what);
+
+// Device allocation tracked in the context.
+template <class T>
+T *ctx_alloc(km_ctx *ctx, size_t count)
+{
+    void *p = nullptr;
+    if (count == 0)
+        count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess)
+        return nullptr;
+    ctx->mem.ptrs.push_back(p);
+    ctx->mem.bytes += count * sizeof(T);
+    return (T *)p;
+}
+
+// sort.hip
+size_t radix_scratch_words(int64_t n);
+hipError_t radix_sort_u32(uint32_t *keys, int32_t *vals, uint32_t *keys_tmp, int32_t *vals_tmp, int64_t n,
+                          int bits, uint32_t *hist, uint32_t *scan_tmp, hipStream_t s, bool *result_in_tmp);
+hipError_t exclusive_scan_u32(uint32_t *data, int64_t n, uint32_t *tmp, hipStream_t s);
+size_t scan_scratch_words(int64_t n);
+
+// leaves.hip
+km_status build_leaves(km_ctx *ctx, const void *points);
+
+// tree.hip
+km_status build_centroid_tree(km_ctx *ctx, const double *c_in);
+hipError_t tree_setup();
+int tree_small_k();
+
+// assign.hip
+km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse);
+
+// reduce.hip
+km_status run_finalize(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out);
+km_status scatter_assignment(km_ctx *ctx, int32_t *assign_out);
+
+} // namespace ekm

@@ -1,0 +1,362 @@
+// Point index, built once per context (Algorithm 1 builds its point tree
+// once, before the iteration loop; the node layout of the point index in the
+// subsection on indexes over spatial vectors and centroids).
+//
+// GPU realisation: points are sorted along a Morton curve over the data
+// bounding box, and cut into leaves that are the largest Morton cells
+// (quadtree / octree cells) holding at most f points.  A leaf is a contiguous
+// run of the sorted points, so a wave reads it with coalesced loads; each leaf
+// keeps its exact FP32 bounding box (the box plays the role of the paper's
+// ball pivot and radius) and the exact fixed-point sum of its points, so a
+// leaf that falls wholly into one cluster updates that cluster's sum without
+// reading its points (the paper's node-level sum-vector update).
+#include <math.h>
+#include <string.h>
+
+#include "ekm_internal.hpp"
+
+namespace ekm {
+
+// ------------------------------------------------------------ input scan
+struct ScanOut {
+    int32_t lo[3], hi[3]; // order-preserving integer images of float bounds
+    int32_t nonfinite;
+    int32_t neg_elsb; // max over nonzero coordinates of -(exponent of lowest set bit)
+    int32_t emsb;     // max over nonzero coordinates of exponent of highest set bit
+    int32_t any_nonzero;
+};
+
+// Order-preserving map float -> int32 (an involution on negative values).
+__device__ inline int32_t ord_of(float f)
+{
+    int32_t i = __float_as_int(f);
+    return i >= 0 ? i : (i ^ 0x7fffffff);
+}
+__host__ inline float float_of_ord(int32_t o)
+{
+    int32_t i = o >= 0 ? o : (o ^ 0x7fffffff);
+    float f;
+    __builtin_memcpy(&f, &i, 4);
+    return f;
+}
+
+template <class T, int D>
+__global__ void __launch_bounds__(256) k_scan_points(const T *x, int64_t n, ScanOut *out)
+{
+    float lo[D], hi[D];
+    for (int i = 0; i < D; ++i) {
+        lo[i] = INFINITY;
+        hi[i] = -INFINITY;
+    }
+    int nonfin = 0, nelsb = -100000, emsb = -100000, anynz = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = 0; i < D; ++i) {
+            T v = x[p * D + i];
+            if (!isfinite(v)) {
+                nonfin = 1;
+                continue;
+            }
+            float fv = (float)v;
+            lo[i] = fminf(lo[i], fv);
+            hi[i] = fmaxf(hi[i], fv);
+            if (v != (T)0) {
+                int el, em;
+                if (sizeof(T) == 4)
+                    bits_f32((float)v, el, em);
+                else
+                    bits_f64((double)v, el, em);
+                nelsb = max(nelsb, -el);
+                emsb = max(emsb, em);
+                anynz = 1;
+            }
+        }
+    }
+    // the box is over the FP32 images of the coordinates, which is what
+    // the Morton keys quantise
+    for (int i = 0; i < D; ++i) {
+        atomicMin(&out->lo[i], ord_of(lo[i]));
+        atomicMax(&out->hi[i], ord_of(hi[i]));
+    }
+    if (nonfin)
+        atomicOr(&out->nonfinite, 1);
+    if (anynz) {
+        atomicMax(&out->neg_elsb, nelsb);
+        atomicMax(&out->emsb, emsb);
+        atomicOr(&out->any_nonzero, 1);
+    }
+}
+
+// ------------------------------------------------------------ keys, gather
+template <class T, int D>
+__global__ void __launch_bounds__(256) k_point_keys(const T *x, int64_t n, Grid g, uint32_t *keys, int32_t *vals)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    float q[D];
+    for (int i = 0; i < D; ++i)
+        q[i] = (float)x[p * D + i];
+    keys[p] = morton_key<D>(q, g);
+    vals[p] = (int32_t)p;
+}
+
+template <class T, int D>
+__global__ void __launch_bounds__(256) k_gather(const T *x, const int32_t *perm, int64_t n, T *xs)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    int64_t src = perm[p];
+    for (int i = 0; i < D; ++i)
+        xs[(int64_t)i * n + p] = x[src * D + i];
+}
+
+// ------------------------------------------------------------ leaf cut
+// Position i starts a new leaf iff the deepest Morton cell shared by points
+// i-1 and i holds more than f points: then i-1 and i lie in different
+// children of that cell, and their leaves (the largest cells with <= f
+// points) differ.  Equal keys beyond f points are cut every f points.
+template <int D>
+__global__ void __launch_bounds__(256) k_leaf_flags(const uint32_t *keys, int64_t n, int f, uint32_t *flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    if (i == 0) {
+        flag[0] = 1;
+        return;
+    }
+    const int KB = key_bits(D);
+    uint32_t a = keys[i - 1], b = keys[i];
+    uint32_t out;
+    if (a == b) {
+        int64_t lo = 0, hi = i; // first index with key == b
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < b)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int64_t rs = lo;
+        lo = i;
+        hi = n; // first index with key > b
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] <= b)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int64_t cntr = lo - rs;
+        out = (cntr > f && ((i - rs) % f) == 0) ? 1u : 0u;
+    } else {
+        int lcp = __clz((int)(a ^ b)) - (32 - KB);
+        int P = (lcp / D) * D; // bits of the deepest shared cell
+        const uint32_t keymask = KB == 32 ? ~0u : ((1u << (KB & 31)) - 1u);
+        uint32_t mask = P == 0 ? 0u : ((~0u) << (KB - P)) & keymask;
+        uint32_t cell = b & mask;
+        int64_t wlo = i - 1 - f < 0 ? 0 : i - 1 - f;
+        int64_t lo = wlo, hi = i - 1; // first index in [wlo, i-1] inside the cell
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((keys[mid] & mask) < cell)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int64_t s = lo;
+        int64_t whi = i + f + 1 > n ? n : i + f + 1;
+        lo = i;
+        hi = whi; // first index in [i, whi) past the cell
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((keys[mid] & mask) <= cell)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        out = (lo - s > f) ? 1u : 0u;
+    }
+    flag[i] = out;
+}
+
+__global__ void __launch_bounds__(256) k_leaf_starts(const uint32_t *flag, const uint32_t *scan, int64_t n,
+                                                     int32_t *leaf_start, int64_t L)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i])
+        leaf_start[scan[i]] = (int32_t)i;
+    if (i == 0)
+        leaf_start[L] = (int32_t)n;
+}
+
+// One wave per leaf: exact FP32 box and exact fixed-point coordinate sums.
+template <int D>
+__global__ void __launch_bounds__(256) k_leaf_info(const float *xs, int64_t n, const int32_t *leaf_start, int64_t L,
+                                                   int S, float4 *box, int64_t *leaf_sum)
+{
+    int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (l >= L)
+        return; // whole wave leaves together
+    int lane = lane_id();
+    int32_t s = leaf_start[l], e = leaf_start[l + 1];
+    bool valid = s + lane < e;
+    float lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+    for (int i = 0; i < D; ++i) {
+        float v = valid ? xs[(int64_t)i * n + s + lane] : 0.0f;
+        int64_t h, q;
+        fix_split_f32(v, S, h, q);
+        h = wave_sum_i64(valid ? h : 0);
+        q = wave_sum_i64(valid ? q : 0);
+        float mn = wave_min_f32(valid ? v : INFINITY);
+        float mx = -wave_min_f32(valid ? -v : INFINITY);
+        lo[i] = mn;
+        hi[i] = mx;
+        if (lane == 0) {
+            leaf_sum[(l * D + i) * 2] = h;
+            leaf_sum[(l * D + i) * 2 + 1] = q;
+        }
+    }
+    if (lane == 0) {
+        box[2 * l] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+        box[2 * l + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    }
+}
+
+// ------------------------------------------------------------ driver
+static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <class T, int D>
+static km_status build_leaves_t(km_ctx *ctx, const T *x)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t n = ctx->n;
+    // 1. input scan
+    ScanOut h0;
+    for (int i = 0; i < 3; ++i) {
+        h0.lo[i] = 0x7fffffff;
+        h0.hi[i] = (int32_t)0x80000000;
+    }
+    h0.nonfinite = 0;
+    h0.neg_elsb = -100000;
+    h0.emsb = -100000;
+    h0.any_nonzero = 0;
+    ScanOut *d0 = ctx_alloc<ScanOut>(ctx, 1);
+    if (!d0) {
+        set_error("kmeans_init: device allocation failed");
+        return KM_ERR_OOM;
+    }
+    if (!hip_ok(hipMemcpyAsync(d0, &h0, sizeof(h0), hipMemcpyHostToDevice, st), "hipMemcpyAsync"))
+        return KM_ERR_HIP;
+    unsigned g = nblocks(n, 256);
+    if (g > 4096)
+        g = 4096;
+    hipLaunchKernelGGL((k_scan_points<T, D>), dim3(g), dim3(256), 0, st, x, n, d0);
+    if (!hip_ok(hipMemcpyAsync(&h0, d0, sizeof(h0), hipMemcpyDeviceToHost, st), "hipMemcpyAsync") ||
+        !hip_ok(hipStreamSynchronize(st), "hipStreamSynchronize"))
+        return KM_ERR_HIP;
+    if (h0.nonfinite) {
+        set_error("kmeans_init: points contain NaN or Inf");
+        return KM_ERR_INVALID;
+    }
+    // exact-sum window
+    int S = h0.any_nonzero ? h0.neg_elsb : 0;
+    int logn = 0;
+    while (((int64_t)1 << logn) < n)
+        ++logn;
+    int W = h0.any_nonzero ? h0.emsb + 1 + S + logn : 0;
+    if (W > MAX_FIX_BITS) {
+        set_error("kmeans_init: coordinates span " + std::to_string(W) +
+                  " bits of fixed point; exact centroid sums support at most " + std::to_string(MAX_FIX_BITS));
+        return KM_ERR_NOT_EXACT;
+    }
+    ctx->S = S;
+    for (int i = 0; i < D; ++i) {
+        float lo = float_of_ord(h0.lo[i]), hi = float_of_ord(h0.hi[i]);
+        ctx->grid.lo[i] = lo;
+        float ext = hi - lo;
+        ctx->grid.scale[i] = ext > 0.0f ? (float)(1u << morton_bits(D)) / ext : 0.0f;
+    }
+    // 2. Morton sort
+    uint32_t *keys = ctx_alloc<uint32_t>(ctx, n), *keys2 = ctx_alloc<uint32_t>(ctx, n);
+    int32_t *vals2 = ctx_alloc<int32_t>(ctx, n);
+    ctx->perm = ctx_alloc<int32_t>(ctx, n);
+    int64_t hist_len = (int64_t)radix_scratch_words(n);
+    uint32_t *hist = ctx_alloc<uint32_t>(ctx, hist_len);
+    uint32_t *scan_tmp = ctx_alloc<uint32_t>(ctx, scan_scratch_words(hist_len > n ? hist_len : n));
+    if (!keys || !keys2 || !vals2 || !ctx->perm || !hist || !scan_tmp) {
+        set_error("kmeans_init: device allocation failed");
+        return KM_ERR_OOM;
+    }
+    hipLaunchKernelGGL((k_point_keys<T, D>), dim3(nblocks(n, 256)), dim3(256), 0, st, x, n, ctx->grid, keys,
+                       ctx->perm);
+    bool in_tmp = false;
+    if (!hip_ok(radix_sort_u32(keys, ctx->perm, keys2, vals2, n, key_bits(D), hist, scan_tmp, st, &in_tmp),
+                "radix sort"))
+        return KM_ERR_HIP;
+    uint32_t *skeys = in_tmp ? keys2 : keys;    // sorted keys
+    uint32_t *flag = in_tmp ? keys : keys2;     // free buffer
+    uint32_t *scan = (uint32_t *)vals2;         // free once perm is in place
+    if (in_tmp &&
+        !hip_ok(hipMemcpyAsync(ctx->perm, vals2, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "copy"))
+        return KM_ERR_HIP;
+    // 3. gather to SoA
+    T *xs = ctx_alloc<T>(ctx, (size_t)n * D);
+    if (!xs) {
+        set_error("kmeans_init: device allocation failed");
+        return KM_ERR_OOM;
+    }
+    ctx->xs = xs;
+    hipLaunchKernelGGL((k_gather<T, D>), dim3(nblocks(n, 256)), dim3(256), 0, st, x, ctx->perm, n, xs);
+    // 4. leaves
+    hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n, ctx->f, flag);
+    if (!hip_ok(hipMemcpyAsync(scan, flag, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy") ||
+        !hip_ok(exclusive_scan_u32(scan, n, scan_tmp, st), "scan"))
+        return KM_ERR_HIP;
+    uint32_t last[2];
+    if (!hip_ok(hipMemcpyAsync(&last[0], scan + n - 1, 4, hipMemcpyDeviceToHost, st), "copy") ||
+        !hip_ok(hipMemcpyAsync(&last[1], flag + n - 1, 4, hipMemcpyDeviceToHost, st), "copy") ||
+        !hip_ok(hipStreamSynchronize(st), "sync"))
+        return KM_ERR_HIP;
+    int64_t L = (int64_t)last[0] + last[1];
+    ctx->L = L;
+    ctx->leaf_start = ctx_alloc<int32_t>(ctx, L + 1);
+    if (!ctx->leaf_start) {
+        set_error("kmeans_init: device allocation failed");
+        return KM_ERR_OOM;
+    }
+    hipLaunchKernelGGL(k_leaf_starts, dim3(nblocks(n, 256)), dim3(256), 0, st, flag, scan, n, ctx->leaf_start, L);
+    if (sizeof(T) == 4 && ctx->cfg.algo == KM_INDEXED) {
+        ctx->leaf_box = (float *)ctx_alloc<float4>(ctx, 2 * L);
+        ctx->leaf_sum = ctx_alloc<int64_t>(ctx, (size_t)L * D * 2);
+        if (!ctx->leaf_box || !ctx->leaf_sum) {
+            set_error("kmeans_init: device allocation failed");
+            return KM_ERR_OOM;
+        }
+        hipLaunchKernelGGL((k_leaf_info<D>), dim3(nblocks(L * WAVE, 256)), dim3(256), 0, st, (const float *)xs, n,
+                           ctx->leaf_start, L, S, (float4 *)ctx->leaf_box, ctx->leaf_sum);
+    }
+    // keep the sort scratch for the centroid sort of large k
+    ctx->ckey = keys;
+    ctx->ckey2 = keys2;
+    ctx->cval2 = vals2;
+    ctx->rs_hist = hist;
+    ctx->rs_hist_len = hist_len;
+    ctx->scan_tmp = scan_tmp;
+    if (!hip_ok(hipGetLastError(), "leaf build launch"))
+        return KM_ERR_HIP;
+    return KM_OK;
+}
+
+km_status build_leaves(km_ctx *ctx, const void *points)
+{
+    const bool f32 = ctx->cfg.point_dtype == KM_F32;
+    if (ctx->d == 2)
+        return f32 ? build_leaves_t<float, 2>(ctx, (const float *)points)
+                   : build_leaves_t<double, 2>(ctx, (const double *)points);
+    return f32 ? build_leaves_t<float, 3>(ctx, (const float *)points)
+               : build_leaves_t<double, 3>(ctx, (const double *)points);
+}
+
+} // namespace ekm
