@@ -63,7 +63,15 @@ typedef enum {
 } km_algo;
 
 /* flags */
-#define KM_FLAG_SSE 1u  /* also compute the objective sum_i D(x_i, c_in[a(i)]) each step */
+#define KM_FLAG_SSE 1u    /* also compute the objective sum_i D(x_i, c_in[a(i)]) each step */
+#define KM_FLAG_TIMING 2u /* record HIP events around each phase of every step (see
+                             kmeans_phase_times); costs a few microseconds per step */
+
+/* Phases of one step, in order, for kmeans_phase_times. */
+#define KM_PHASE_TREE 0   /* fl32 centroids, norm bound, centroid tree */
+#define KM_PHASE_ASSIGN 1 /* candidate search, assignment, FP64 recheck, exact accumulation */
+#define KM_PHASE_UPDATE 2 /* centroid refinement and statistics */
+#define KM_NPHASE 3
 
 typedef struct km_config {
     int32_t d;           /* point dimension: 2 or 3 */
@@ -89,6 +97,7 @@ typedef struct km_iter_stats {
     int64_t rechecked;          /* points whose FP32 margin fell under the error bound and
                                    were decided by canonical FP64 distances */
     int64_t cand_total;         /* sum over leaves of candidate-list lengths */
+    int64_t leaves;             /* leaves of the point index (0 on the brute path) */
     double sse;                 /* sum_i D(x_i, c_in[a(i)]) if KM_FLAG_SSE, else 0 */
 } km_iter_stats;
 
@@ -132,6 +141,14 @@ EKM_API km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, in
  * per_iter asks for host data. */
 EKM_API km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t max_iter,
                      int32_t stop_when_stable, int32_t *iters_done, km_iter_stats *per_iter);
+
+/* GPU time per phase summed over the steps recorded since the previous call
+ * (only steps of a context created with KM_FLAG_TIMING are recorded).
+ *   ms:    host array of KM_NPHASE doubles, milliseconds per phase.
+ *   steps: host, number of steps summed.
+ * Synchronises the context's stream and clears the record.
+ * Errors: KM_ERR_INVALID (null argument), KM_ERR_HIP. */
+EKM_API km_status kmeans_phase_times(km_ctx *ctx, double *ms, int64_t *steps);
 
 /* Release the context and its workspace (synchronises its stream).  NULL is a no-op. */
 EKM_API km_status kmeans_destroy(km_ctx *ctx);

@@ -15,9 +15,11 @@ from ._binding import (  # noqa: F401
     KM_F32,
     KM_F64,
     KM_FLAG_SSE,
+    KM_FLAG_TIMING,
     KM_INDEXED,
     KM_OK,
     LIB_PATH,
+    PHASES,
     Context,
     Distortion,
     EKMError,
@@ -28,6 +30,7 @@ from ._binding import (  # noqa: F401
     kmeans_destroy,
     kmeans_init,
     kmeans_last_error,
+    kmeans_phase_times,
     kmeans_run,
     kmeans_step,
     kmeans_workspace_bytes,

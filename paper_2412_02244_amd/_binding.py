@@ -21,9 +21,11 @@ KM_OK, KM_ERR_INVALID, KM_ERR_OOM, KM_ERR_HIP, KM_ERR_UNSUPPORTED, KM_ERR_NOT_EX
 KM_F64, KM_F32 = 0, 1
 KM_BRUTE, KM_INDEXED = 0, 1
 KM_FLAG_SSE = 1
+KM_FLAG_TIMING = 2
+PHASES = ("tree", "assign", "update")
 
 EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy",
-            "distortion_fwd", "distortion_bwd", "kmeans_last_error")
+            "kmeans_phase_times", "distortion_fwd", "distortion_bwd", "kmeans_last_error")
 
 
 class EKMError(RuntimeError):
@@ -41,7 +43,7 @@ class KmConfig(ctypes.Structure):
 class KmIterStats(ctypes.Structure):
     _fields_ = [("n_changed", ctypes.c_int64), ("dist_evals", ctypes.c_int64), ("brute_evals", ctypes.c_int64),
                 ("single_cand_points", ctypes.c_int64), ("rechecked", ctypes.c_int64),
-                ("cand_total", ctypes.c_int64), ("sse", ctypes.c_double)]
+                ("cand_total", ctypes.c_int64), ("leaves", ctypes.c_int64), ("sse", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -65,10 +67,12 @@ def load_library(path: str = LIB_PATH):
     lib.kmeans_step.argtypes = [P, P, P, P, ctypes.POINTER(KmIterStats)]
     lib.kmeans_run.argtypes = [P, P, P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(KmIterStats)]
     lib.kmeans_destroy.argtypes = [P]
+    lib.kmeans_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
     lib.distortion_fwd.argtypes = [P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.distortion_bwd.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.kmeans_last_error.restype = ctypes.c_char_p
-    for name in ("kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy", "distortion_fwd", "distortion_bwd"):
+    for name in ("kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy", "kmeans_phase_times",
+                 "distortion_fwd", "distortion_bwd"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -170,6 +174,14 @@ def kmeans_run(ctx: Context, c_inout: torch.Tensor, max_iter: int, stop_when_sta
 
 def kmeans_destroy(ctx: Context):
     ctx.close()
+
+
+def kmeans_phase_times(ctx: Context):
+    """GPU milliseconds per phase summed since the last call -> (dict, steps)."""
+    ms = (ctypes.c_double * len(PHASES))()
+    steps = ctypes.c_int64(0)
+    _check(load_library().kmeans_phase_times(ctypes.c_void_p(ctx.handle), ms, ctypes.byref(steps)))
+    return {name: ms[i] for i, name in enumerate(PHASES)}, steps.value
 
 
 def distortion_fwd(x: torch.Tensor, c: torch.Tensor):

@@ -92,13 +92,14 @@ static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
     int64_t L = n;                        // leaves <= n
     b += (size_t)(L + 1) * 4;             // leaf_start
     if (cfg->algo == KM_INDEXED) {
-        b += (size_t)L * (32 + d * 16 + 4 + 4 + 4 * CAND_CAP); // box, sums, prev, ncand, cand
-        int64_t nb = (k + TREE_BUCKET - 1) / TREE_BUCKET;
-        b += ((size_t)1 << (ceil_log2(nb) + 1)) * 32; // node boxes
-        b += (size_t)k * 16;                          // cs
+        b += (size_t)L * (32 + d * 16 + 4);            // leaf box, exact sums, previous whole-leaf cluster
+        b += (size_t)((L + GROUP_LEAVES - 1) / GROUP_LEAVES) * 32; // group boxes
+        TreeArgs T;
+        tree_layout(k, T);
+        b += (size_t)T.nnodes * 32 + (size_t)k * 16;  // node boxes, tree-ordered centroids
     }
     b += (size_t)k * (16 + 4 + d * 16 + 4); // c32, cval, acc, cnt
-    int64_t nblk = cfg->algo == KM_INDEXED ? (L * WAVE + 255) / 256 : (n + 255) / 256;
+    int64_t nblk = cfg->algo == KM_INDEXED ? (L + GROUP_LEAVES - 1) / GROUP_LEAVES : (n + 255) / 256;
     b += (size_t)nblk * (NSTAT * 8 + 8);
     b += 4096;
     return b;
@@ -126,11 +127,41 @@ size_t kmeans_workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
 
 const char *kmeans_last_error(void) { return g_error.c_str(); }
 
+km_status kmeans_phase_times(km_ctx *ctx, double *ms, int64_t *steps)
+{
+    if (!ctx || !ms || !steps) {
+        set_error("kmeans_phase_times: null argument");
+        return KM_ERR_INVALID;
+    }
+    if (!hip_ok(hipStreamSynchronize(ctx->stream), "kmeans_phase_times: hipStreamSynchronize"))
+        return KM_ERR_HIP;
+    for (int p = 0; p < KM_NPHASE; ++p)
+        ms[p] = 0.0;
+    for (auto &ev : ctx->ev_steps) {
+        for (int p = 0; p < KM_NPHASE; ++p) {
+            float t = 0.0f;
+            if (!hip_ok(hipEventElapsedTime(&t, ev[p], ev[p + 1]), "kmeans_phase_times: hipEventElapsedTime"))
+                return KM_ERR_HIP;
+            ms[p] += t;
+        }
+        for (auto e : ev)
+            ctx->ev_pool.push_back(e);
+    }
+    *steps = (int64_t)ctx->ev_steps.size();
+    ctx->ev_steps.clear();
+    return KM_OK;
+}
+
 km_status kmeans_destroy(km_ctx *ctx)
 {
     if (!ctx)
         return KM_OK;
     hipStreamSynchronize(ctx->stream);
+    for (auto &ev : ctx->ev_steps)
+        for (auto e : ev)
+            hipEventDestroy(e);
+    for (auto e : ctx->ev_pool)
+        hipEventDestroy(e);
     for (void *p : ctx->mem.ptrs)
         hipFree(p);
     if (ctx->host_stat)
@@ -198,17 +229,13 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
         return alloc_fail(nullptr);
     }
     if (cfg->algo == KM_INDEXED) {
-        int64_t nb = (k + TREE_BUCKET - 1) / TREE_BUCKET;
-        ctx->nbuckets = nb;
-        ctx->tree_h = ceil_log2(nb);
-        ctx->nnodes = (int64_t)2 << ctx->tree_h;
-        ctx->cs = ctx_alloc<float4>(ctx, k);
-        ctx->node_lo = ctx_alloc<float4>(ctx, ctx->nnodes);
-        ctx->node_hi = ctx_alloc<float4>(ctx, ctx->nnodes);
+        TreeArgs &T = ctx->tree;
+        tree_layout(k, T);
+        T.cs = ctx_alloc<float4>(ctx, k);
+        T.node_lo = ctx_alloc<float4>(ctx, T.nnodes);
+        T.node_hi = ctx_alloc<float4>(ctx, T.nnodes);
         ctx->leaf_prev = ctx_alloc<int32_t>(ctx, L);
-        ctx->cand = ctx_alloc<int32_t>(ctx, (size_t)L * CAND_CAP);
-        ctx->ncand = ctx_alloc<int32_t>(ctx, L);
-        if (!ctx->cs || !ctx->node_lo || !ctx->node_hi || !ctx->leaf_prev || !ctx->cand || !ctx->ncand) {
+        if (!T.cs || !T.node_lo || !T.node_hi || !ctx->leaf_prev) {
             kmeans_destroy(ctx);
             return alloc_fail(nullptr);
         }
@@ -248,17 +275,40 @@ km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *a
         return KM_ERR_INVALID;
     }
     km_status s = KM_OK;
+    const bool timing = (ctx->cfg.flags & KM_FLAG_TIMING) != 0;
+    std::array<hipEvent_t, KM_NPHASE + 1> ev{};
+    if (timing) {
+        for (auto &e : ev) {
+            if (!ctx->ev_pool.empty()) {
+                e = ctx->ev_pool.back();
+                ctx->ev_pool.pop_back();
+            } else if (!hip_ok(hipEventCreate(&e), "kmeans_step: hipEventCreate")) {
+                return KM_ERR_HIP;
+            }
+        }
+        ctx->ev_steps.push_back(ev);
+    }
+    auto mark = [&](int i) {
+        if (timing)
+            hipEventRecord(ev[i], ctx->stream);
+    };
+    mark(KM_PHASE_TREE);
     if (ctx->cfg.point_dtype == KM_F32) {
         s = build_centroid_tree(ctx, c_in);
         if (s != KM_OK)
             return s;
     }
+    mark(KM_PHASE_ASSIGN);
     bool want_sse = (ctx->cfg.flags & KM_FLAG_SSE) != 0;
     s = run_assign(ctx, c_in, want_sse);
     if (s != KM_OK)
         return s;
-    s = run_finalize(ctx, c_in, c_out, assign_out);
+    mark(KM_PHASE_UPDATE);
+    s = run_finalize(ctx, c_in, c_out, nullptr);
     if (s != KM_OK)
+        return s;
+    mark(KM_NPHASE);
+    if (assign_out && (s = scatter_assignment(ctx, assign_out)) != KM_OK)
         return s;
     ctx->steps_done++;
     if (stats) {
@@ -277,6 +327,7 @@ km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *a
         stats->single_cand_points = h[ST_SINGLE];
         stats->rechecked = h[ST_RECHECK];
         stats->cand_total = h[ST_CANDS];
+        stats->leaves = ctx->cfg.algo == KM_INDEXED ? ctx->L : 0;
         double sse;
         memcpy(&sse, h + NSTAT, sizeof(double));
         stats->sse = want_sse ? sse : 0.0;

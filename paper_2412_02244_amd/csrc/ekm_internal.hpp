@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
 #include <string>
 #include <vector>
 
@@ -14,9 +15,10 @@
 namespace ekm {
 
 constexpr int WAVE = 64;
-constexpr int MAX_LEAF = 64;   // a leaf fits one wave
-constexpr int CAND_CAP = 64;   // candidate slots per leaf: one per lane
-constexpr int TREE_BUCKET = 8; // centroids per centroid-tree leaf bucket
+constexpr int MAX_LEAF = 64;     // a leaf fits one wave
+constexpr int GROUP_LEAVES = 64; // consecutive leaves sharing one centroid-tree descent
+constexpr int TREE_BUCKET = 8;   // centroids per centroid-tree leaf bucket
+constexpr int TREE_MAX_LEVELS = 8;
 constexpr int NSTAT = 8;       // per-block statistics slots (see StatSlot)
 constexpr int MAX_FIX_BITS = 94;
 
@@ -26,7 +28,7 @@ enum StatSlot {
     ST_SINGLE = 2,
     ST_RECHECK = 3,
     ST_CANDS = 4,
-    ST_OVERFLOW_PTS = 5,
+    ST_FALLBACK_PTS = 5, // points decided by a fallback search (group candidate set too large)
 };
 
 // ------------------------------------------------------------------------
@@ -307,6 +309,12 @@ __device__ inline double fix_to_double(int64_t hi, int64_t lo, int S)
 // ------------------------------------------------------------------------
 __device__ inline int lane_id() { return (int)__lane_id(); }
 
+// A value every lane of the workgroup holds the same copy of (read from LDS
+// after a barrier), made visibly uniform to the compiler.  Loops and
+// branches around __syncthreads() must depend only on such values, or the
+// compiler may treat them as divergent and split the barrier across lanes.
+__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 __device__ inline int64_t wave_sum_i64(int64_t v)
@@ -373,6 +381,17 @@ __device__ inline void wave_accumulate(bool valid, int a, const int64_t (&hi)[D]
     }
 }
 
+// Implicit 8-ary centroid tree (see tree.hip).
+struct TreeArgs {
+    float4 *cs;               // [k] fl32 centroids in tree order, w = centroid id bits
+    float4 *node_lo, *node_hi; // [nnodes] level 0 (buckets) first
+    int nlev;                 // levels, the last one is the root
+    int start;                // lowest level with at most 256 nodes
+    int64_t nnodes;
+    int64_t lev_size[TREE_MAX_LEVELS];
+    int64_t lev_off[TREE_MAX_LEVELS];
+};
+
 // ------------------------------------------------------------------------
 // Context
 // ------------------------------------------------------------------------
@@ -406,14 +425,11 @@ struct km_ctx {
     float4 *c32 = nullptr;        // [k] fl32(c) in caller order
     uint32_t *ckey = nullptr, *ckey2 = nullptr;
     int32_t *cval = nullptr, *cval2 = nullptr;
-    float4 *cs = nullptr;         // [k] fl32 centroids in tree order (w = id as int bits)
-    int tree_h = 0;               // leaf level of the implicit binary tree
-    int64_t nbuckets = 0, nnodes = 0;
-    float4 *node_lo = nullptr, *node_hi = nullptr; // [nnodes]
-    float *cerr = nullptr;        // [1] bound on ||c - fl32(c)||
-    // A2: candidates
-    int32_t *cand = nullptr;      // [L][CAND_CAP]
-    int32_t *ncand = nullptr;     // [L]  (> CAND_CAP means overflow)
+    ekm::TreeArgs tree{};
+    float *cerr = nullptr;        // [1] bits of an FP32 upper bound on max_j ||c_j||
+    // groups of GROUP_LEAVES consecutive leaves
+    int64_t ngroups = 0;
+    float4 *group_box = nullptr;  // [ngroups][2]
     // A5: exact sums
     int64_t *acc = nullptr;       // [k][d][2]
     int32_t *cnt = nullptr;       // [k]
@@ -429,6 +445,9 @@ struct km_ctx {
     uint32_t *scan_tmp = nullptr;
     ekm::Scratch mem;
     int steps_done = 0;
+    // KM_FLAG_TIMING: five events per recorded step (phase boundaries)
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::array<hipEvent_t, KM_NPHASE + 1>> ev_steps;
 };
 
 namespace ekm {
@@ -463,7 +482,7 @@ km_status build_leaves(km_ctx *ctx, const void *points);
 // tree.hip
 km_status build_centroid_tree(km_ctx *ctx, const double *c_in);
 hipError_t tree_setup();
-int tree_small_k();
+void tree_layout(int64_t k, TreeArgs &T);
 
 // assign.hip
 km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse);

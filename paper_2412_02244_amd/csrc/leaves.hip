@@ -72,7 +72,19 @@ __global__ void __launch_bounds__(256) k_scan_points(const T *x, int64_t n, Scan
         }
     }
     // the box is over the FP32 images of the coordinates, which is what
-    // the Morton keys quantise
+    // the Morton keys quantise; one lane per wave publishes the wave's result
+    for (int i = 0; i < D; ++i) {
+        lo[i] = wave_min_f32(lo[i]);
+        hi[i] = -wave_min_f32(-hi[i]);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        nonfin |= __shfl_xor(nonfin, o);
+        nelsb = max(nelsb, __shfl_xor(nelsb, o));
+        emsb = max(emsb, __shfl_xor(emsb, o));
+        anynz |= __shfl_xor(anynz, o);
+    }
+    if (lane_id() != 0)
+        return;
     for (int i = 0; i < D; ++i) {
         atomicMin(&out->lo[i], ord_of(lo[i]));
         atomicMax(&out->hi[i], ord_of(hi[i]));
@@ -224,6 +236,27 @@ __global__ void __launch_bounds__(256) k_leaf_info(const float *xs, int64_t n, c
     }
 }
 
+// One thread per group: union of its leaves' boxes.
+__global__ void __launch_bounds__(256) k_group_boxes(const float4 *leaf_box, int64_t L, int64_t ngroups,
+                                                     float4 *group_box)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngroups)
+        return;
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f), hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    for (int64_t l = g * GROUP_LEAVES; l < L && l < (g + 1) * GROUP_LEAVES; ++l) {
+        float4 a = leaf_box[2 * l], b = leaf_box[2 * l + 1];
+        lo.x = fminf(lo.x, a.x);
+        lo.y = fminf(lo.y, a.y);
+        lo.z = fminf(lo.z, a.z);
+        hi.x = fmaxf(hi.x, b.x);
+        hi.y = fmaxf(hi.y, b.y);
+        hi.z = fmaxf(hi.z, b.z);
+    }
+    group_box[2 * g] = lo;
+    group_box[2 * g + 1] = hi;
+}
+
 // ------------------------------------------------------------ driver
 static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
@@ -250,8 +283,8 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
     if (!hip_ok(hipMemcpyAsync(d0, &h0, sizeof(h0), hipMemcpyHostToDevice, st), "hipMemcpyAsync"))
         return KM_ERR_HIP;
     unsigned g = nblocks(n, 256);
-    if (g > 4096)
-        g = 4096;
+    if (g > 1024)
+        g = 1024;
     hipLaunchKernelGGL((k_scan_points<T, D>), dim3(g), dim3(256), 0, st, x, n, d0);
     if (!hip_ok(hipMemcpyAsync(&h0, d0, sizeof(h0), hipMemcpyDeviceToHost, st), "hipMemcpyAsync") ||
         !hip_ok(hipStreamSynchronize(st), "hipStreamSynchronize"))
@@ -336,6 +369,14 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         }
         hipLaunchKernelGGL((k_leaf_info<D>), dim3(nblocks(L * WAVE, 256)), dim3(256), 0, st, (const float *)xs, n,
                            ctx->leaf_start, L, S, (float4 *)ctx->leaf_box, ctx->leaf_sum);
+        ctx->ngroups = (L + GROUP_LEAVES - 1) / GROUP_LEAVES;
+        ctx->group_box = ctx_alloc<float4>(ctx, 2 * ctx->ngroups);
+        if (!ctx->group_box) {
+            set_error("kmeans_init: device allocation failed");
+            return KM_ERR_OOM;
+        }
+        hipLaunchKernelGGL(k_group_boxes, dim3(nblocks(ctx->ngroups, 256)), dim3(256), 0, st,
+                           (const float4 *)ctx->leaf_box, L, ctx->ngroups, ctx->group_box);
     }
     // keep the sort scratch for the centroid sort of large k
     ctx->ckey = keys;

@@ -46,34 +46,38 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, do
         cnt[j] = 0;
         return;
     }
-    // statistics block
-    __shared__ long long red[FIN_THREADS];
+    // statistics block: each thread folds whole rows (NSTAT counters) of the
+    // per-block partials, then a fixed-shape tree combines the threads
+    __shared__ long long red[NSTAT][FIN_THREADS];
     __shared__ double dred[FIN_THREADS];
-    for (int q = 0; q < NSTAT; ++q) {
-        long long s = 0;
-        for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x)
-            s += stat_part[b * NSTAT + q];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o)
-                red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0)
-            stat_out[q] = red[0];
-        __syncthreads();
-    }
+    long long acc8[NSTAT];
+    for (int q = 0; q < NSTAT; ++q)
+        acc8[q] = 0;
     double s = 0.0;
-    for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x)
+    for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x) {
+        const longlong2 *row = (const longlong2 *)(stat_part + b * NSTAT);
+#pragma unroll
+        for (int q = 0; q < NSTAT / 2; ++q) {
+            longlong2 v = row[q];
+            acc8[2 * q] += v.x;
+            acc8[2 * q + 1] += v.y;
+        }
         s += sse_part[b];
+    }
+    for (int q = 0; q < NSTAT; ++q)
+        red[q][threadIdx.x] = acc8[q];
     dred[threadIdx.x] = s;
     __syncthreads();
     for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
+        if ((int)threadIdx.x < o) {
+            for (int q = 0; q < NSTAT; ++q)
+                red[q][threadIdx.x] += red[q][threadIdx.x + o];
             dred[threadIdx.x] += dred[threadIdx.x + o];
+        }
         __syncthreads();
     }
+    if (threadIdx.x < NSTAT)
+        stat_out[threadIdx.x] = red[threadIdx.x][0];
     if (threadIdx.x == 0) {
         *sse_out = dred[0];
         *cmax_bits = 0u; // the next centroid tree recomputes the norm bound

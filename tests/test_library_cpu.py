@@ -30,8 +30,8 @@ def _declared():
 
 def test_header_declares_the_abi():
     names = _declared()
-    assert set(names) == {"kmeans_workspace_bytes", "kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy",
-                          "distortion_fwd", "distortion_bwd", "kmeans_last_error"}
+    import paper_2412_02244_amd as ekm
+    assert set(names) == set(ekm.EXPORTED)
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -93,6 +93,7 @@ def test_null_pointers_rejected(lib):
     assert lib.kmeans_step(None, None, None, None, None) == ekm.KM_ERR_INVALID
     assert lib.kmeans_run(None, None, None, 1, 0, None, None) == ekm.KM_ERR_INVALID
     assert lib.kmeans_destroy(None) == ekm.KM_OK
+    assert lib.kmeans_phase_times(None, None, None) == ekm.KM_ERR_INVALID
     assert lib.distortion_fwd(None, None, 1, 1, 1, 1, 3, None, None, None) == ekm.KM_ERR_INVALID
     assert lib.distortion_fwd(ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 1, 1, 1, 4, ctypes.c_void_p(16),
                               ctypes.c_void_p(16), None) == ekm.KM_ERR_INVALID
