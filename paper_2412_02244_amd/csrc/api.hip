@@ -93,13 +93,13 @@ static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
     b += (size_t)(L + 1) * 4;             // leaf_start
     if (cfg->algo == KM_INDEXED) {
         b += (size_t)L * (32 + d * 16 + 4);            // leaf box, exact sums, previous whole-leaf cluster
-        b += (size_t)((L + GROUP_LEAVES - 1) / GROUP_LEAVES) * 32; // group boxes
+        b += (size_t)L * 36 + 4;                      // groups (at most one per leaf): boxes, first leaves
         TreeArgs T;
         tree_layout(k, T);
         b += (size_t)T.nnodes * 32 + (size_t)k * 16;  // node boxes, tree-ordered centroids
     }
     b += (size_t)k * (16 + 4 + d * 16 + 4); // c32, cval, acc, cnt
-    int64_t nblk = cfg->algo == KM_INDEXED ? (L + GROUP_LEAVES - 1) / GROUP_LEAVES : (n + 255) / 256;
+    int64_t nblk = cfg->algo == KM_INDEXED ? L : (n + 255) / 256; // statistics rows: groups or blocks
     b += (size_t)nblk * (NSTAT * 8 + 8);
     b += 4096;
     return b;

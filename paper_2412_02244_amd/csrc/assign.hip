@@ -2,32 +2,12 @@
 // search over the centroid index), fused with the accumulation half of the
 // centroid update.
 //
-// k_assign_groups: one workgroup per group of GROUP_LEAVES consecutive
-// leaves (Morton order keeps them spatially close).
-//
-//  1. Group search.  For the group's bounding box B the workgroup descends
-//     the 8-ary centroid tree level by level.  U is the smallest FP32
-//     max-distance from B to a node or centroid seen so far: every node box
-//     contains a centroid, so U bounds the distance from every point of B to
-//     some centroid (the paper inherits such upper bounds from parent nodes,
-//     Eq. (7)).  Nodes and centroids whose FP32 min-distance to B exceeds
-//     prune_threshold(U) are dropped (the node pruning of Eq. (8), made
-//     conservative for rounding).  The survivors form the group list S.
-//  2. Leaf filter.  For a leaf box b inside B, the same rule applied to S
-//     alone gives exactly the leaf's candidates over all k centroids: any
-//     centroid outside S has min-distance to b at least its min-distance to
-//     B, above prune_threshold(U_B) >= prune_threshold(U_b), while the
-//     centroid that realised U_B is in S and bounds U_b.  One wave handles a
-//     leaf; lanes test S in chunks of 64 and ballots give the candidate set.
-//  3. A leaf with one candidate is assigned to it without a single distance
-//     evaluation (Eq. (6)'s batch assignment) and adds its precomputed exact
-//     sum to that cluster.  Otherwise each lane (one point) scans the
-//     candidates in FP32; a point whose best-vs-second margin is below the
-//     error bound is decided again with canonical FP64 distances.
-//
-// If S (or the descent frontier) does not fit in LDS, the group repeats the
-// search leaf by leaf, and a leaf that still does not fit scans all k
-// centroids; results are the same, only slower.
+// k_assign_waves: one wave per group of GROUP_LEAVES consecutive leaves;
+// see the comment at the kernel.  U, the smallest FP32 max-distance from a
+// box to a node or centroid seen so far, bounds the distance from every
+// point of the box to some centroid (the paper inherits such bounds from
+// parent nodes, Eq. (7)); nodes and centroids whose FP32 min-distance to the
+// box exceeds prune_threshold(U) are dropped.
 //
 // k_assign_brute32 / k_assign_brute64: Lloyd's assignment over all k
 // centroids staged through LDS tiles (the GPU baseline; FP64 is the plain
@@ -37,10 +17,14 @@
 namespace ekm {
 
 constexpr int ASSIGN_THREADS = 256;
-constexpr int G_WAVES = ASSIGN_THREADS / WAVE;
-constexpr int LPW = GROUP_LEAVES / G_WAVES; // leaves per wave
-constexpr int S_CAP = 1024;                 // group candidate list in LDS
-constexpr int F_CAP = 1024;                 // descent frontier in LDS
+constexpr int G_WAVES = ASSIGN_THREADS / WAVE; // independent waves per workgroup
+constexpr int SW_CAP = 256;                    // per-wave candidate list (LDS)
+constexpr int FR_CH = 8;                       // descent entries per level: FR_CH chunks of 64
+constexpr int FR_CAP = FR_CH * WAVE;
+constexpr int PAR_CAP = FR_CAP / TREE_BUCKET;  // kept parents per level
+static_assert(GROUP_LEAVES <= WAVE, "one lane holds one leaf of the group");
+static_assert(TREE_START_MAX <= FR_CAP, "the first descent level fits the per-lane entries");
+static_assert(MAX_LEAF <= WAVE, "one lane holds one point of a leaf");
 
 struct AssignArgs {
     const void *xs;     // [d][n] Morton order
@@ -55,12 +39,14 @@ struct AssignArgs {
     const float4 *leaf_box;
     const int64_t *leaf_sum;
     int32_t *leaf_prev;
+    const int32_t *group_leaf;
     const float4 *group_box;
     int64_t ngroups;
     // centroid tree
     TreeArgs T;
     // update
     int S;
+    int fix64;
     int64_t *acc;
     int32_t *cnt;
     int64_t *stat_part;
@@ -87,20 +73,23 @@ struct BlockStats {
     double sse[G_WAVES];
 };
 
-struct GroupShared {
-    float4 sc[S_CAP];          // group candidate list: fl32 coordinates, w = centroid id
-    int front[2][F_CAP];       // descent frontier (node indices within a level)
-    float fmind[F_CAP];        // min-distance of each evaluated entry
-    // the group's leaves, loaded once per group (published by the search's barriers)
-    float4 lbox[GROUP_LEAVES][2];
-    int lstart[GROUP_LEAVES + 1];
-    int lprev[GROUP_LEAVES];
-    float red[G_WAVES];
-    int count[2];
-    int overflow;
-    int gid;
-    BlockStats bs;
+// Per-wave LDS of the indexed kernel.  Only lanes of the owning wave touch
+// it; writes by some lanes are read by others only after wave_sync().
+struct WaveShared {
+    float4 sc[SW_CAP];    // candidate list of the current box: fl32 coordinates, w = centroid id
+    int par[2][PAR_CAP];  // kept nodes of the previous descent level
 };
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes
+// (the LDS executes one wave's operations in issue order; the fences keep
+// the compiler from moving accesses across).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 
 __device__ inline void stats_begin(BlockStats &bs)
 {
@@ -135,121 +124,130 @@ __device__ inline void stats_end(BlockStats &bs, const AssignArgs &A, const int6
     }
 }
 
-// Block-wide minimum (all threads call; result returned to all).
-__device__ inline float block_min(float v, float *red)
+// One wave's counters (wave-uniform values) and per-lane SSE terms ->
+// partial row `row` (lanes 0..NSTAT-1 store).
+__device__ inline void wave_stats_end(const AssignArgs &A, const int64_t (&c)[NSTAT], double sse, int64_t row)
 {
-    v = wave_min_f32(v);
-    __syncthreads(); // red may still be read by the previous call
+    int64_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < NSTAT; ++q)
+        if (lane_id() == q)
+            mine = c[q];
+    const double ws = A.want_sse ? wave_sum_f64(sse) : 0.0;
+    if (lane_id() < NSTAT)
+        A.stat_part[row * NSTAT + lane_id()] = mine;
     if (lane_id() == 0)
-        red[threadIdx.x / WAVE] = v;
-    __syncthreads();
-    float m = red[0];
-    for (int w = 1; w < G_WAVES; ++w)
-        m = fminf(m, red[w]);
-    return m;
+        A.sse_part[row] = ws;
 }
 
-// ------------------------------------------------------------- group search
-// Fills sh.sc with the candidate list of box [lo, hi]; returns its length,
-// or -1 if the frontier or the list would not fit.  All threads call.
+// Number of lanes of the wave with `p` set (wave-uniform).
+__device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
+
+// ------------------------------------------------------------- tree search
+// Fills sh.sc with the candidate list of box [lo, hi] and returns its
+// length, or -1 if a descent level or the list does not fit.  The whole
+// wave calls; the result is uniform.
+//
+// The descent starts at the lowest tree level with at most FR_CAP nodes and
+// evaluates every node there; each later level evaluates the children of
+// the nodes kept at the level above, and the last step the centroids of the
+// kept buckets.  U is the smallest box-to-node max-distance seen at any
+// level (a valid bound: every node holds a centroid).
 template <int D>
-__device__ int block_search(const float *lo, const float *hi, const AssignArgs &A, float e, GroupShared &sh)
+__device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A, float e, WaveShared &sh)
 {
     const TreeArgs &T = A.T;
-    const int tid = threadIdx.x;
-    float U = INFINITY;
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    wave_sync(); // earlier readers of sh are done
     int level = T.start;
+    int np = -1; // kept parents at the level above (-1: the start level is evaluated densely)
     int cur = 0;
-    int F = (int)T.lev_size[level];
-    __syncthreads(); // the previous search's readers are done with sh
-    for (int i = tid; i < F; i += ASSIGN_THREADS)
-        sh.front[cur][i] = i;
-    if (tid == 0)
-        sh.overflow = 0;
-    __syncthreads();
-    // internal levels and the bucket level
+    float U = INFINITY;
     while (true) {
-        const int64_t off = T.lev_off[level];
+        const int64_t off = T.lev_off[level], lsz = T.lev_size[level];
+        const int F = np < 0 ? (int)lsz : np * TREE_BUCKET;
+        float mv[FR_CH];
+        int nv[FR_CH];
         float Ul = INFINITY;
-        for (int i = tid; i < F; i += ASSIGN_THREADS) {
-            int64_t node = off + sh.front[cur][i];
-            float nl[3], nh[3];
-            f4_to(T.node_lo[node], nl);
-            f4_to(T.node_hi[node], nh);
-            sh.fmind[i] = bb_mind<D>(lo, hi, nl, nh);
-            Ul = fminf(Ul, bb_maxd<D>(lo, hi, nl, nh));
-        }
-        U = fminf(U, block_min(Ul, sh.red));
-        const float thr = prune_threshold(U, e);
-        const int nxt = cur ^ 1;
-        if (tid == 0)
-            sh.count[nxt] = 0;
-        __syncthreads();
-        if (level > 0) {
-            const int64_t csz = T.lev_size[level - 1];
-            for (int i = tid; i < F; i += ASSIGN_THREADS) {
-                if (sh.fmind[i] <= thr) {
-                    int64_t first = 8 * (int64_t)sh.front[cur][i];
-                    int nch = (int)((csz - first) < 8 ? (csz - first) : 8);
-                    int pos = atomicAdd(&sh.count[nxt], nch);
-                    if (pos + nch <= F_CAP) {
-                        for (int c = 0; c < nch; ++c)
-                            sh.front[nxt][pos + c] = (int)(first + c);
-                    } else {
-                        sh.overflow = 1;
-                    }
+#pragma unroll
+        for (int c = 0; c < FR_CH; ++c) {
+            mv[c] = INFINITY;
+            nv[c] = -1;
+            const int i = c * WAVE + lane;
+            if (c * WAVE < F && i < F) {
+                const int64_t node = np < 0 ? i : (int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
+                if (node < lsz) {
+                    float nl[3], nh[3];
+                    f4_to(T.node_lo[off + node], nl);
+                    f4_to(T.node_hi[off + node], nh);
+                    mv[c] = bb_mind<D>(lo, hi, nl, nh);
+                    nv[c] = (int)node;
+                    Ul = fminf(Ul, bb_maxd<D>(lo, hi, nl, nh));
                 }
             }
-        } else {
-            // surviving buckets, kept as bucket indices
-            for (int i = tid; i < F; i += ASSIGN_THREADS)
-                if (sh.fmind[i] <= thr) {
-                    int pos = atomicAdd(&sh.count[nxt], 1);
-                    sh.front[nxt][pos] = sh.front[cur][i]; // pos < F <= F_CAP
-                }
         }
-        __syncthreads();
-        if (uniform_int(sh.overflow))
+        U = fminf(U, wave_min_f32(Ul));
+        const float thr = prune_threshold(U, e);
+        const int nxt = cur ^ 1;
+        int cnt = 0;
+#pragma unroll
+        for (int c = 0; c < FR_CH; ++c) {
+            if (c * WAVE < F) {
+                const bool keep = nv[c] >= 0 && mv[c] <= thr;
+                const uint64_t mk = __ballot(keep);
+                const int pos = cnt + __popcll(mk & lt);
+                if (keep && pos < PAR_CAP)
+                    sh.par[nxt][pos] = nv[c];
+                cnt += __popcll(mk);
+            }
+        }
+        if (cnt > PAR_CAP)
             return -1;
+        wave_sync();
+        np = cnt;
         cur = nxt;
-        F = uniform_int(sh.count[cur]);
         if (level == 0)
             break;
         --level;
     }
-    // centroids of the surviving buckets
-    const int nent = F * TREE_BUCKET;
-    if (nent > F_CAP)
-        return -1;
+    // centroids of the kept buckets
+    const int F = np * TREE_BUCKET;
+    float mv[FR_CH];
+    float4 cv[FR_CH];
     float Ul = INFINITY;
-    for (int i = tid; i < nent; i += ASSIGN_THREADS) {
-        int64_t t = (int64_t)sh.front[cur][i / TREE_BUCKET] * TREE_BUCKET + (i % TREE_BUCKET);
-        float m = INFINITY;
-        if (t < A.k) {
-            float c[3];
-            f4_to(T.cs[t], c);
-            m = box_mind<D>(lo, hi, c);
-            Ul = fminf(Ul, box_maxd<D>(lo, hi, c));
+#pragma unroll
+    for (int c = 0; c < FR_CH; ++c) {
+        mv[c] = INFINITY;
+        cv[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const int i = c * WAVE + lane;
+        if (c * WAVE < F && i < F) {
+            const int64_t t = (int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
+            if (t < A.k) {
+                cv[c] = T.cs[t];
+                float cc[3];
+                f4_to(cv[c], cc);
+                mv[c] = box_mind<D>(lo, hi, cc);
+                Ul = fminf(Ul, box_maxd<D>(lo, hi, cc));
+            }
         }
-        sh.fmind[i] = m;
     }
-    U = fminf(U, block_min(Ul, sh.red));
+    U = fminf(U, wave_min_f32(Ul));
     const float thr = prune_threshold(U, e);
-    if (tid == 0)
-        sh.count[0] = 0;
-    __syncthreads();
-    for (int i = tid; i < nent; i += ASSIGN_THREADS) {
-        if (sh.fmind[i] <= thr) {
-            int64_t t = (int64_t)sh.front[cur][i / TREE_BUCKET] * TREE_BUCKET + (i % TREE_BUCKET);
-            int pos = atomicAdd(&sh.count[0], 1);
-            if (pos < S_CAP)
-                sh.sc[pos] = T.cs[t];
-            else
-                sh.overflow = 1;
+    int cnt = 0;
+#pragma unroll
+    for (int c = 0; c < FR_CH; ++c) {
+        if (c * WAVE < F) {
+            const bool keep = mv[c] <= thr;
+            const uint64_t mk = __ballot(keep);
+            const int pos = cnt + __popcll(mk & lt);
+            if (keep && pos < SW_CAP)
+                sh.sc[pos] = cv[c];
+            cnt += __popcll(mk);
         }
     }
-    __syncthreads();
-    return uniform_int(sh.overflow) ? -1 : uniform_int(sh.count[0]);
+    wave_sync();
+    return cnt > SW_CAP ? -1 : cnt;
 }
 
 // --------------------------------------------------------------- epilogue
@@ -300,56 +298,127 @@ __device__ inline int brute64_all(const double (&xd)[D], const AssignArgs &A)
     return bj;
 }
 
+// Exact accumulation of one leaf's points (lane = point, `valid` lanes are
+// the whole leaf) into their clusters.  The clusters present are taken one
+// at a time; a cluster's coordinate sums are wave sums of the points'
+// fixed-point values (one int64 per coordinate when every value fits
+// FIX64_BITS bits, else the hi/lo parts), its count a ballot popcount.  The
+// last cluster gets the leaf's precomputed exact sum minus what the others
+// took.  The values are then split into the (hi, lo) accumulator form and
+// lanes 0..2D-1 (sums) and 2D (count) add them with integer atomics.
 template <int D>
-__device__ void process_leaf_all(int64_t l, const AssignArgs &A, float e, int64_t (&st)[NSTAT], double &sse);
+__device__ inline void accumulate_leaf(bool valid, int a, const float (&x)[D], const int64_t *lsum,
+                                       const AssignArgs &A)
+{
+    const int lane = lane_id();
+    int64_t v0[D], v1[D]; // fix64: value, 0; else hi, lo
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (A.fix64) {
+            v0[i] = valid ? fix_f32(x[i], A.S) : 0;
+            v1[i] = 0;
+        } else {
+            fix_split_f32(x[i], A.S, v0[i], v1[i]);
+            if (!valid)
+                v0[i] = v1[i] = 0;
+        }
+    }
+    int64_t took_hi[D], took_lo[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        took_hi[i] = took_lo[i] = 0;
+    uint64_t active = __ballot(valid);
+    while (active) {
+        const int c = rl_i(a, __ffsll((unsigned long long)active) - 1);
+        const bool in = valid && a == c;
+        const uint64_t grp = __ballot(in);
+        active &= ~grp;
+        int64_t sh[D], sl[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            if (active == 0) {
+                sh[i] = lsum[2 * i] - took_hi[i];
+                sl[i] = lsum[2 * i + 1] - took_lo[i];
+            } else if (A.fix64) {
+                const int64_t t = wave_sum_i64(in ? v0[i] : 0);
+                sh[i] = t >> 32; // floor, so that sl is in [0, 2^32)
+                sl[i] = t - (sh[i] << 32);
+            } else {
+                sh[i] = wave_sum_i64(in ? v0[i] : 0);
+                sl[i] = wave_sum_i64(in ? v1[i] : 0);
+            }
+            took_hi[i] += sh[i];
+            took_lo[i] += sl[i];
+        }
+        int64_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            if (lane == 2 * i)
+                mine = sh[i];
+            if (lane == 2 * i + 1)
+                mine = sl[i];
+        }
+        if (lane < 2 * D)
+            atomicAdd((unsigned long long *)&A.acc[(int64_t)c * D * 2 + lane], (unsigned long long)mine);
+        else if (lane == 2 * D)
+            atomicAdd(&A.cnt[c], __popcll(grp));
+    }
+}
 
 // ------------------------------------------------------------- leaves
-// Candidate filter of one leaf against the group list (one wave): returns
-// the candidate count and the first candidate's list index; the threshold
-// is returned for the mask pass.
+// The wave's list is read in chunks of 64 entries, lane j holding entry
+// 64c + j in registers; a candidate is then broadcast to all lanes with
+// readlane (scalar operands, no LDS round trip per candidate).
+__device__ inline float4 list_entry(const WaveShared &sh, int j, int sn)
+{
+    return j < sn ? sh.sc[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Candidate filter of one leaf box against the wave's list (sn entries):
+// returns the candidate count m, the id of the first candidate (the only
+// one when m == 1) and the threshold for the later mask passes.
 template <int D>
-__device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, float e, const GroupShared &sh,
-                                  float &thr, int &first)
+__device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, float e, const WaveShared &sh,
+                                  float &thr, int &j1)
 {
     const int lane = lane_id();
     const int nch = (sn + WAVE - 1) / WAVE;
     float U = INFINITY;
     for (int c = 0; c < nch; ++c) {
-        int j = c * WAVE + lane;
-        if (j < sn) {
-            float cc[3];
-            f4_to(sh.sc[j], cc);
+        const int j = c * WAVE + lane;
+        const float4 c4 = list_entry(sh, j, sn);
+        float cc[3];
+        f4_to(c4, cc);
+        if (j < sn)
             U = fminf(U, box_maxd<D>(blo, bhi, cc));
-        }
     }
     thr = prune_threshold(wave_min_f32(U), e);
     int m = 0;
-    first = -1;
+    j1 = -1;
     for (int c = 0; c < nch; ++c) {
-        int j = c * WAVE + lane;
-        bool keep = false;
-        if (j < sn) {
-            float cc[3];
-            f4_to(sh.sc[j], cc);
-            keep = box_mind<D>(blo, bhi, cc) <= thr;
-        }
-        unsigned long long mk = __ballot(keep);
-        if (mk && first < 0)
-            first = c * WAVE + __ffsll(mk) - 1;
+        const int j = c * WAVE + lane;
+        const float4 c4 = list_entry(sh, j, sn);
+        float cc[3];
+        f4_to(c4, cc);
+        const bool keep = j < sn && box_mind<D>(blo, bhi, cc) <= thr;
+        const uint64_t mk = __ballot(keep);
+        if (mk && j1 < 0)
+            j1 = rl_i(__float_as_int(c4.w), __ffsll((unsigned long long)mk) - 1);
         m += __popcll(mk);
     }
     return m;
 }
 
 // FP32 scan of one point (one lane) against the leaf's candidates: the list
-// entries of the group list within `thr` of the leaf box.  The candidate
-// masks are rebuilt chunk by chunk with ballots, so every lane holds them
-// in registers (lanes never hand data to each other through LDS).  A point
-// whose best-vs-second margin is below the error bound is decided again
-// with canonical FP64 distances.  Returns the centroid id.
+// entries within `thr` of the leaf box, in chunks, each candidate broadcast
+// from the lane that holds it.  Lanes whose best-vs-second margin is below
+// the error bound are decided again with canonical FP64 distances over the
+// candidates that can still be nearest: those whose FP32 lower bound does
+// not exceed the best one's upper bound (any other is strictly farther in
+// exact and in FP64 arithmetic).  Returns the centroid id.
 template <int D>
 __device__ inline int assign_point(const float (&x)[D], bool valid, const float *blo, const float *bhi, float thr,
-                                   int sn, float e, const AssignArgs &A, const GroupShared &sh,
+                                   int sn, float e, const AssignArgs &A, const WaveShared &sh,
                                    int64_t (&st)[NSTAT])
 {
     const int lane = lane_id();
@@ -358,228 +427,89 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
     int id1 = 0x7fffffff;
     for (int c = 0; c < nch; ++c) {
         const int jl = c * WAVE + lane;
-        bool keep = false;
-        if (jl < sn) {
-            float cc[3];
-            f4_to(sh.sc[jl], cc);
-            keep = box_mind<D>(blo, bhi, cc) <= thr;
-        }
-        unsigned long long mk = __ballot(keep);
+        const float4 c4 = list_entry(sh, jl, sn);
+        float cl[3];
+        f4_to(c4, cl);
+        uint64_t mk = __ballot(jl < sn && box_mind<D>(blo, bhi, cl) <= thr);
         while (mk) {
-            int b = __ffsll(mk) - 1;
+            const int b = __ffsll((unsigned long long)mk) - 1;
             mk &= mk - 1;
-            float4 c4 = sh.sc[c * WAVE + b];
-            float cc[3];
-            f4_to(c4, cc);
-            int cid = __float_as_int(c4.w);
-            float sv = sqdist32<D>(x, cc);
-            if (sv < s1 || (sv == s1 && cid < id1)) {
-                s2 = s1;
-                s1 = sv;
-                id1 = cid;
-            } else {
-                s2 = fminf(s2, sv);
+            float cc[3] = {rl_f(c4.x, b), rl_f(c4.y, b), D == 3 ? rl_f(c4.z, b) : 0.0f};
+            const int cid = rl_i(__float_as_int(c4.w), b);
+            const float sv = sqdist32<D>(x, cc);
+            const bool better = sv < s1 || (sv == s1 && cid < id1);
+            s2 = better ? s1 : fminf(s2, sv);
+            s1 = better ? sv : s1;
+            id1 = better ? cid : id1;
+        }
+    }
+    const bool re = valid && !margin_safe(s1, s2, e);
+    const int nre = wave_count(re);
+    if (nre == 0)
+        return id1;
+    st[ST_RECHECK] += nre;
+    double xd[D];
+    for (int i = 0; i < D; ++i)
+        xd[i] = (double)x[i];
+    const float hi1 = dist_hi(s1, e);
+    double bd = INFINITY;
+    int bj = 0x7fffffff;
+    for (int c = 0; c < nch; ++c) {
+        const int jl = c * WAVE + lane;
+        const float4 c4 = list_entry(sh, jl, sn);
+        float cl[3];
+        f4_to(c4, cl);
+        uint64_t mk = __ballot(jl < sn && box_mind<D>(blo, bhi, cl) <= thr);
+        while (mk) {
+            const int b = __ffsll((unsigned long long)mk) - 1;
+            mk &= mk - 1;
+            float cc[3] = {rl_f(c4.x, b), rl_f(c4.y, b), D == 3 ? rl_f(c4.z, b) : 0.0f};
+            const int cid = rl_i(__float_as_int(c4.w), b);
+            if (re && dist_lo(sqdist32<D>(x, cc), e) <= hi1) {
+                const double Dv = sqdist64<D>(xd, A.c_in + (int64_t)cid * D);
+                if (Dv < bd || (Dv == bd && cid < bj)) {
+                    bd = Dv;
+                    bj = cid;
+                }
             }
         }
     }
-    if (valid && !margin_safe(s1, s2, e)) {
-        double xd[D];
-        for (int i = 0; i < D; ++i)
+    return re ? bj : id1;
+}
+
+// Epilogue of a leaf assigned point by point: record changed assignments
+// (aold: the previous assignments, loaded by the caller), SSE terms, exact
+// cluster sums.
+template <int D>
+__device__ inline void leaf_finish(const AssignArgs &A, int64_t l, bool valid, int64_t p, const float (&x)[D],
+                                   int best, int aold, int64_t (&st)[NSTAT], double &sse)
+{
+    const bool ch = valid && aold != best;
+    if (ch)
+        A.a[p] = best;
+    st[ST_CHANGED] += wave_count(ch);
+    if (A.want_sse && valid) {
+        double xd[D], cd[D];
+        for (int i = 0; i < D; ++i) {
             xd[i] = (double)x[i];
-        double bd = INFINITY;
-        int bj = 0x7fffffff;
-        for (int j = 0; j < sn; ++j) {
-            float4 c4 = sh.sc[j];
-            float cc[3];
-            f4_to(c4, cc);
-            if (!(box_mind<D>(blo, bhi, cc) <= thr))
-                continue;
-            int cid = __float_as_int(c4.w);
-            double Dv = sqdist64<D>(xd, A.c_in + (int64_t)cid * D);
-            if (Dv < bd || (Dv == bd && cid < bj)) {
-                bd = Dv;
-                bj = cid;
-            }
+            cd[i] = A.c_in[(int64_t)best * D + i];
         }
-        ++st[ST_RECHECK];
-        return bj;
+        sse += sqdist64<D>(xd, cd);
     }
-    return id1;
-}
-
-// One wave: its LPW consecutive leaves of the group (leaf indices l0 + t).
-// The candidate filters of all its leaves run first (LDS only); then the
-// leaves are processed in order while the next leaf's points and previous
-// assignments are already being loaded.
-template <int D>
-__device__ inline void load_leaf(int t, int m, int j1, const AssignArgs &A, const GroupShared &sh, float (&xv)[D],
-                                 int &av)
-{
-    const int lane = lane_id();
-    const float *xs = (const float *)A.xs;
-    const int s = sh.lstart[t], size = sh.lstart[t + 1] - s;
-    const int64_t p = (int64_t)s + lane;
-    const bool valid = lane < size;
-    const bool need_x = m != 1 || A.want_sse;
-    const bool need_a = m != 1 || sh.lprev[t] != j1;
-    av = -1;
-    for (int i = 0; i < D; ++i)
-        xv[i] = 0.0f;
-    if (valid && need_x)
-        for (int i = 0; i < D; ++i)
-            xv[i] = xs[(int64_t)i * A.n + p];
-    if (valid && need_a)
-        av = A.a[p];
-}
-
-template <int D>
-__device__ void process_wave_leaves(int64_t l0, int nl, int sn, const AssignArgs &A, float e, GroupShared &sh,
-                                    int64_t (&st)[NSTAT], double &sse)
-{
-    const int lane = lane_id();
-    const int tb = (threadIdx.x / WAVE) * LPW;
-    const int te = (tb + LPW < nl) ? tb + LPW : nl;
-    // filter every leaf first; lane r keeps leaf tb + r's results
-    float r_thr = 0.0f;
-    int r_m = 0, r_j = -1;
-    for (int t = tb; t < te; ++t) {
-        float blo[3], bhi[3];
-        f4_to(sh.lbox[t][0], blo);
-        f4_to(sh.lbox[t][1], bhi);
-        float thr;
-        int first;
-        const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, first);
-        const int j1 = m == 1 ? __float_as_int(sh.sc[first].w) : -1;
-        if (lane == t - tb) {
-            r_thr = thr;
-            r_m = m;
-            r_j = j1;
-        }
-    }
-    if (tb >= te)
-        return;
-    float xn[D];
-    int an;
-    load_leaf<D>(tb, __shfl(r_m, 0), __shfl(r_j, 0), A, sh, xn, an);
-    for (int t = tb; t < te; ++t) {
-        float x[D];
-        for (int i = 0; i < D; ++i)
-            x[i] = xn[i];
-        const int aold = an;
-        const int m = __shfl(r_m, t - tb), j1 = __shfl(r_j, t - tb);
-        const float thr = __shfl(r_thr, t - tb);
-        if (t + 1 < te)
-            load_leaf<D>(t + 1, __shfl(r_m, t + 1 - tb), __shfl(r_j, t + 1 - tb), A, sh, xn, an);
-        const int64_t l = l0 + t;
-        const int s = sh.lstart[t], size = sh.lstart[t + 1] - s;
-        const int64_t p = (int64_t)s + lane;
-        const bool valid = lane < size;
-        if (lane == 0)
-            st[ST_CANDS] += m;
-        if (m == 1) {
-            const int j = j1;
-            if (sh.lprev[t] != j) {
-                if (valid && aold != j) {
-                    A.a[p] = j;
-                    ++st[ST_CHANGED];
-                }
-                if (lane == 0)
-                    A.leaf_prev[l] = j;
-            }
-            if (lane == 0) {
-                int64_t *ac = A.acc + (int64_t)j * D * 2;
-                for (int i = 0; i < 2 * D; ++i)
-                    atomicAdd((unsigned long long *)&ac[i], (unsigned long long)A.leaf_sum[l * D * 2 + i]);
-                atomicAdd(&A.cnt[j], size);
-                st[ST_SINGLE] += size;
-            }
-            if (A.want_sse && valid) {
-                double xd[D], cd[D];
-                for (int i = 0; i < D; ++i) {
-                    xd[i] = (double)x[i];
-                    cd[i] = A.c_in[(int64_t)j * D + i];
-                }
-                sse += sqdist64<D>(xd, cd);
-            }
-            continue;
-        }
-        if (m == 0) { // cannot happen for a well-formed tree; stay in bounds regardless
-            process_leaf_all<D>(l, A, e, st, sse);
-            continue;
-        }
-        if (lane == 0 && sh.lprev[t] != -1)
-            A.leaf_prev[l] = -1;
-        float blo[3], bhi[3];
-        f4_to(sh.lbox[t][0], blo);
-        f4_to(sh.lbox[t][1], bhi);
-        const int best = assign_point<D>(x, valid, blo, bhi, thr, sn, e, A, sh, st);
-        if (lane == 0)
-            st[ST_EVALS] += (int64_t)m * size;
-        if (valid && aold != best) {
-            A.a[p] = best;
-            ++st[ST_CHANGED];
-        }
-        if (A.want_sse && valid) {
-            double xd[D], cd[D];
-            for (int i = 0; i < D; ++i) {
-                xd[i] = (double)x[i];
-                cd[i] = A.c_in[(int64_t)best * D + i];
-            }
-            sse += sqdist64<D>(xd, cd);
-        }
-        int64_t hi[D], lo[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-            fix_split_f32(x[i], A.S, hi[i], lo[i]);
-        wave_accumulate<D>(valid, best, hi, lo, A.acc, A.cnt);
-    }
-}
-
-// One wave, one leaf (the per-leaf fallback when the group list overflows).
-template <int D>
-__device__ void process_leaf(int64_t l, int sn, const AssignArgs &A, float e, GroupShared &sh,
-                             int64_t (&st)[NSTAT], double &sse)
-{
-    const int lane = lane_id();
-    const float *xs = (const float *)A.xs;
-    const int32_t s = A.leaf_start[l], size = A.leaf_start[l + 1] - s;
-    const bool valid = lane < size;
-    const int64_t p = (int64_t)s + lane;
-    float blo[3], bhi[3];
-    f4_to(A.leaf_box[2 * l], blo);
-    f4_to(A.leaf_box[2 * l + 1], bhi);
-    float thr;
-    int first;
-    const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, first);
-    if (m == 0) {
-        process_leaf_all<D>(l, A, e, st, sse);
-        return;
-    }
-    if (lane == 0) {
-        st[ST_CANDS] += m;
-        st[ST_EVALS] += (int64_t)m * size;
-        A.leaf_prev[l] = -1;
-    }
-    float x[D];
-    for (int i = 0; i < D; ++i)
-        x[i] = valid ? xs[(int64_t)i * A.n + p] : 0.0f;
-    const int best = assign_point<D>(x, valid, blo, bhi, thr, sn, e, A, sh, st);
-    int64_t ch = 0;
-    finish_point<D, float>(A, valid, p, x, best, ch, sse);
-    st[ST_CHANGED] += ch;
+    accumulate_leaf<D>(valid, best, x, A.leaf_sum + l * D * 2, A);
 }
 
 // Fallback for a leaf whose candidate list does not fit: scan all k
 // centroids in FP32 (fl32 copies from global memory), same margin rule.
 template <int D>
-__device__ void process_leaf_all(int64_t l, const AssignArgs &A, float e, int64_t (&st)[NSTAT], double &sse)
+__device__ void process_leaf_all(int64_t l, int s, int size, int prev, const AssignArgs &A, float e,
+                                 int64_t (&st)[NSTAT], double &sse)
 {
     const int lane = lane_id();
     const float *xs = (const float *)A.xs;
-    const int32_t s = A.leaf_start[l], size = A.leaf_start[l + 1] - s;
     const bool valid = lane < size;
     const int64_t p = (int64_t)s + lane;
-    if (lane == 0 && A.leaf_prev[l] != -1)
+    if (lane == 0 && prev != -1)
         A.leaf_prev[l] = -1;
     float x[D];
     for (int i = 0; i < D; ++i)
@@ -605,62 +535,225 @@ __device__ void process_leaf_all(int64_t l, const AssignArgs &A, float e, int64_
         for (int i = 0; i < D; ++i)
             xd[i] = (double)x[i];
         best = brute64_all<D>(xd, A);
-        ++st[ST_RECHECK];
     }
-    if (valid) {
-        st[ST_EVALS] += A.k;
-        ++st[ST_FALLBACK_PTS];
-    }
-    int64_t ch = 0;
-    finish_point<D, float>(A, valid, p, x, best, ch, sse);
-    st[ST_CHANGED] += ch;
+    const int nv = wave_count(valid);
+    st[ST_RECHECK] += wave_count(re);
+    st[ST_EVALS] += (int64_t)nv * A.k;
+    st[ST_FALLBACK_PTS] += nv;
+    leaf_finish<D>(A, l, valid, p, x, best, valid ? A.a[p] : -1, st, sse);
 }
 
+// Per-leaf data held by lane t of the wave for leaf l0 + t of its group.
+struct LeafRegs {
+    float lo[3], hi[3];
+    int start, size, prev;
+};
+
 template <int D>
-__global__ void __launch_bounds__(ASSIGN_THREADS, 4) k_assign_groups(AssignArgs A)
+__device__ inline void leaf_of(const LeafRegs &r, int t, float *blo, float *bhi)
 {
-    __shared__ GroupShared sh;
-    const int tid = threadIdx.x, wid = tid / WAVE;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        blo[i] = rl_f(r.lo[i], t);
+        bhi[i] = rl_f(r.hi[i], t);
+    }
+}
+
+// One leaf against the wave's list (the per-leaf path: no prefetch).
+template <int D>
+__device__ void process_leaf(int64_t l, const LeafRegs &r, int t, int sn, const AssignArgs &A, float e,
+                             const WaveShared &sh, int64_t (&st)[NSTAT], double &sse)
+{
+    const int lane = lane_id();
+    const float *xs = (const float *)A.xs;
+    const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
+    float blo[3], bhi[3];
+    leaf_of<D>(r, t, blo, bhi);
+    float thr;
+    int j1;
+    const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
+    if (m == 0) {
+        process_leaf_all<D>(l, s, size, prev, A, e, st, sse);
+        return;
+    }
+    const bool valid = lane < size;
+    const int64_t p = (int64_t)s + lane;
+    st[ST_CANDS] += m;
+    st[ST_EVALS] += (int64_t)m * size;
+    if (lane == 0 && prev != -1)
+        A.leaf_prev[l] = -1;
+    float x[D];
+    for (int i = 0; i < D; ++i)
+        x[i] = valid ? xs[(int64_t)i * A.n + p] : 0.0f;
+    const int aold = valid ? A.a[p] : -1;
+    const int best = assign_point<D>(x, valid, blo, bhi, thr, sn, e, A, sh, st);
+    leaf_finish<D>(A, l, valid, p, x, best, aold, st, sse);
+}
+
+// Points and previous assignments of leaf t, as far as its filter result
+// needs them (a single-candidate leaf that keeps its cluster needs neither).
+template <int D>
+__device__ inline void load_leaf(const LeafRegs &r, int t, int m, int j1, const AssignArgs &A, float (&xv)[D],
+                                 int &av)
+{
+    const int lane = lane_id();
+    const float *xs = (const float *)A.xs;
+    const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
+    const int64_t p = (int64_t)s + lane;
+    const bool valid = lane < size;
+    const bool need_x = m != 1 || A.want_sse;
+    const bool need_a = m != 1 || prev != j1;
+    av = -1;
+    for (int i = 0; i < D; ++i)
+        xv[i] = 0.0f;
+    if (valid && need_x)
+        for (int i = 0; i < D; ++i)
+            xv[i] = xs[(int64_t)i * A.n + p];
+    if (valid && need_a)
+        av = A.a[p];
+}
+
+// k_assign_waves: one wave per group (at most GROUP_LEAVES consecutive
+// leaves inside one compact Morton cell, see leaves.hip); the waves of a
+// workgroup are independent and the kernel has no workgroup barrier.
+//
+//  1. Group search: the centroid-tree descent for the group's bounding box
+//     gives the group list S (kNN-style pruning with the upper bound U, the
+//     node pruning of Eq. (8), made conservative for rounding).
+//  2. Leaf filter: for a leaf box b inside the group box, the same rule
+//     applied to S alone gives exactly the leaf's candidates over all k
+//     centroids: a centroid outside S has min-distance to b at least its
+//     min-distance to the group box, above prune_threshold(U_group) >=
+//     prune_threshold(U_b), and the centroid that realised U_group is in S.
+//     Lanes test S in chunks of 64; ballots give the candidate set.
+//  3. A leaf with one candidate is assigned to it without any distance
+//     evaluation (Eq. (6)'s batch assignment) and adds its precomputed exact
+//     sum to that cluster.  Otherwise each lane (one point) scans the
+//     candidates in FP32; a point whose best-vs-second margin is below the
+//     error bound is decided again with canonical FP64 distances.
+//
+// If S does not fit, the wave searches leaf by leaf, and a leaf whose own
+// list does not fit scans all k centroids; results are the same.
+template <int D>
+__global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
+{
+    __shared__ WaveShared wsh[G_WAVES];
+    const int lane = lane_id();
+    const int64_t g = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
+    if (g >= A.ngroups)
+        return; // whole wave; nothing below synchronises across waves
+    WaveShared &sh = wsh[threadIdx.x / WAVE];
     const float e = err_bound(A.cmax_bits);
-    const int64_t g = blockIdx.x; // one group of leaves per workgroup
-    if (tid < NSTAT)
-        sh.bs.v[tid] = 0;
-    if (tid < G_WAVES)
-        sh.bs.sse[tid] = 0.0;
     int64_t st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
     double sse = 0.0;
-    const int64_t l0 = g * GROUP_LEAVES;
-    const int nl = (int)((l0 + GROUP_LEAVES < A.L) ? GROUP_LEAVES : A.L - l0);
-    if (tid < nl) {
-        sh.lbox[tid][0] = A.leaf_box[2 * (l0 + tid)];
-        sh.lbox[tid][1] = A.leaf_box[2 * (l0 + tid) + 1];
-        sh.lprev[tid] = A.leaf_prev[l0 + tid];
+    const int64_t l0 = A.group_leaf[g];
+    const int nl = A.group_leaf[g + 1] - (int)l0; // 1..GROUP_LEAVES
+    LeafRegs r;
+    for (int i = 0; i < 3; ++i)
+        r.lo[i] = r.hi[i] = 0.0f;
+    r.start = r.size = 0;
+    r.prev = -1;
+    if (lane < nl) {
+        const float4 bl = A.leaf_box[2 * (l0 + lane)], bh = A.leaf_box[2 * (l0 + lane) + 1];
+        f4_to(bl, r.lo);
+        f4_to(bh, r.hi);
+        r.start = A.leaf_start[l0 + lane];
+        r.size = A.leaf_start[l0 + lane + 1] - r.start;
+        r.prev = A.leaf_prev[l0 + lane];
     }
-    if (tid <= nl)
-        sh.lstart[tid] = A.leaf_start[l0 + tid];
     float glo[3], ghi[3];
     f4_to(A.group_box[2 * g], glo);
     f4_to(A.group_box[2 * g + 1], ghi);
-    const int sn = block_search<D>(glo, ghi, A, e, sh); // its barriers publish the leaf data
-    if (sn >= 0) {
-        process_wave_leaves<D>(l0, nl, sn, A, e, sh, st, sse);
-    } else {
-        // the group's list does not fit: search leaf by leaf (uniform loop)
+    const int sn = wave_search<D>(glo, ghi, A, e, sh);
+    if (sn < 0) {
+        // the group's list does not fit: search leaf by leaf
         for (int t = 0; t < nl; ++t) {
-            const int64_t l = l0 + t;
             float blo[3], bhi[3];
-            f4_to(A.leaf_box[2 * l], blo);
-            f4_to(A.leaf_box[2 * l + 1], bhi);
-            const int ln = block_search<D>(blo, bhi, A, e, sh);
-            if (wid == 0) {
-                if (ln >= 0)
-                    process_leaf<D>(l, ln, A, e, sh, st, sse);
-                else
-                    process_leaf_all<D>(l, A, e, st, sse);
-            }
+            leaf_of<D>(r, t, blo, bhi);
+            const int ln = wave_search<D>(blo, bhi, A, e, sh);
+            if (ln >= 0)
+                process_leaf<D>(l0 + t, r, t, ln, A, e, sh, st, sse);
+            else
+                process_leaf_all<D>(l0 + t, rl_i(r.start, t), rl_i(r.size, t), rl_i(r.prev, t), A, e, st, sse);
+        }
+        wave_stats_end(A, st, sse, g);
+        return;
+    }
+    // filter every leaf first; lane t keeps leaf t's results
+    float r_thr = 0.0f;
+    int r_m = 0, r_j = -1;
+    for (int t = 0; t < nl; ++t) {
+        float blo[3], bhi[3];
+        leaf_of<D>(r, t, blo, bhi);
+        float thr;
+        int j1;
+        const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
+        if (m != 1)
+            j1 = -1;
+        if (lane == t) {
+            r_thr = thr;
+            r_m = m;
+            r_j = j1;
         }
     }
-    stats_end(sh.bs, A, st, sse, g);
+    float xn[D];
+    int an;
+    load_leaf<D>(r, 0, rl_i(r_m, 0), rl_i(r_j, 0), A, xn, an);
+    for (int t = 0; t < nl; ++t) {
+        float x[D];
+        for (int i = 0; i < D; ++i)
+            x[i] = xn[i];
+        const int aold = an;
+        const int m = rl_i(r_m, t), j1 = rl_i(r_j, t);
+        const float thr = rl_f(r_thr, t);
+        if (t + 1 < nl)
+            load_leaf<D>(r, t + 1, rl_i(r_m, t + 1), rl_i(r_j, t + 1), A, xn, an);
+        const int64_t l = l0 + t;
+        const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
+        const int64_t p = (int64_t)s + lane;
+        const bool valid = lane < size;
+        st[ST_CANDS] += m;
+        if (m == 1) {
+            const int j = j1;
+            if (prev != j) {
+                const bool ch = valid && aold != j;
+                if (ch)
+                    A.a[p] = j;
+                st[ST_CHANGED] += wave_count(ch);
+                if (lane == 0)
+                    A.leaf_prev[l] = j;
+            }
+            // the leaf's exact sum and count: one atomic per lane
+            if (lane < 2 * D) {
+                int64_t *ac = A.acc + (int64_t)j * D * 2;
+                atomicAdd((unsigned long long *)&ac[lane], (unsigned long long)A.leaf_sum[l * D * 2 + lane]);
+            } else if (lane == 2 * D) {
+                atomicAdd(&A.cnt[j], size);
+            }
+            st[ST_SINGLE] += size;
+            if (A.want_sse && valid) {
+                double xd[D], cd[D];
+                for (int i = 0; i < D; ++i) {
+                    xd[i] = (double)x[i];
+                    cd[i] = A.c_in[(int64_t)j * D + i];
+                }
+                sse += sqdist64<D>(xd, cd);
+            }
+            continue;
+        }
+        if (m == 0) { // cannot happen for a well-formed tree; stay correct regardless
+            process_leaf_all<D>(l, s, size, prev, A, e, st, sse);
+            continue;
+        }
+        if (lane == 0 && prev != -1)
+            A.leaf_prev[l] = -1;
+        float blo[3], bhi[3];
+        leaf_of<D>(r, t, blo, bhi);
+        const int best = assign_point<D>(x, valid, blo, bhi, thr, sn, e, A, sh, st);
+        st[ST_EVALS] += (int64_t)m * size;
+        leaf_finish<D>(A, l, valid, p, x, best, aold, st, sse);
+    }
+    wave_stats_end(A, st, sse, g);
 }
 
 // ------------------------------------------------------------- brute force
@@ -769,10 +862,12 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
     A.leaf_box = (const float4 *)ctx->leaf_box;
     A.leaf_sum = ctx->leaf_sum;
     A.leaf_prev = ctx->leaf_prev;
+    A.group_leaf = ctx->group_leaf;
     A.group_box = ctx->group_box;
     A.ngroups = ctx->ngroups;
     A.T = ctx->tree;
     A.S = ctx->S;
+    A.fix64 = ctx->fix64;
     A.acc = ctx->acc;
     A.cnt = ctx->cnt;
     A.stat_part = ctx->stat_part;
@@ -782,7 +877,7 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
     return A;
 }
 
-// Rows of per-block (brute) or per-group (indexed) statistics partials.
+// Rows of per-block (brute) or per-wave-group (indexed) statistics partials.
 int64_t assign_blocks(const km_ctx *ctx)
 {
     if (ctx->cfg.algo == KM_INDEXED)
@@ -795,12 +890,13 @@ km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse)
     hipStream_t st = ctx->stream;
     AssignArgs A = make_args(ctx, c_in, want_sse);
     unsigned nb = (unsigned)assign_blocks(ctx);
+    const unsigned nwg = (unsigned)((ctx->ngroups + G_WAVES - 1) / G_WAVES);
     const int D = ctx->d;
     if (ctx->cfg.algo == KM_INDEXED) {
         if (D == 2)
-            hipLaunchKernelGGL(k_assign_groups<2>, dim3(nb), dim3(ASSIGN_THREADS), 0, st, A);
+            hipLaunchKernelGGL(k_assign_waves<2>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
         else
-            hipLaunchKernelGGL(k_assign_groups<3>, dim3(nb), dim3(ASSIGN_THREADS), 0, st, A);
+            hipLaunchKernelGGL(k_assign_waves<3>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
     } else if (ctx->cfg.point_dtype == KM_F32) {
         size_t lds = (size_t)ctx->tile * sizeof(float4);
         if (D == 2)

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <array>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -16,11 +17,16 @@ namespace ekm {
 
 constexpr int WAVE = 64;
 constexpr int MAX_LEAF = 64;     // a leaf fits one wave
-constexpr int GROUP_LEAVES = 64; // consecutive leaves sharing one centroid-tree descent
+constexpr int GROUP_LEAVES = 8;  // consecutive leaves sharing one centroid-tree descent (one wave)
+// Group cells: the largest Morton cells with at most this many points (a
+// multiple of the leaf size, so cells are unions of whole leaves).
+inline constexpr int group_cell_points(int f) { return 8 * f; }
 constexpr int TREE_BUCKET = 8;   // centroids per centroid-tree leaf bucket
 constexpr int TREE_MAX_LEVELS = 8;
+constexpr int TREE_START_MAX = 512; // nodes a descent evaluates at its first level
 constexpr int NSTAT = 8;       // per-block statistics slots (see StatSlot)
 constexpr int MAX_FIX_BITS = 94;
+constexpr int FIX64_BITS = 56;  // per-point fixed-point values of this size sum over a wave within int64
 
 enum StatSlot {
     ST_CHANGED = 0,
@@ -220,6 +226,18 @@ __device__ inline void fix_split_f32(float v, int S, int64_t &hi, int64_t &lo)
     lo = (int64_t)(uint32_t)(uint64_t)V;
 }
 
+// The same value as one int64 when it has at most FIX64_BITS bits (the
+// shift is then in [0, FIX64_BITS - 24] or a right shift of trailing zeros).
+__device__ inline int64_t fix_f32(float v, int S)
+{
+    const uint32_t b = __float_as_uint(v);
+    const uint32_t ex = (b >> 23) & 0xffu;
+    const uint32_t m = ex ? ((b & 0x7fffffu) | 0x800000u) : (b & 0x7fffffu);
+    const int sh = (ex ? (int)ex - 150 : -149) + S;
+    const int64_t mag = sh >= 0 ? ((int64_t)m << sh) : (int64_t)(m >> (-sh > 31 ? 31 : -sh));
+    return (b >> 31) ? -mag : mag;
+}
+
 __device__ inline void fix_split_f64(double v, int S, int64_t &hi, int64_t &lo)
 {
     uint64_t b = (uint64_t)__double_as_longlong(v);
@@ -317,33 +335,77 @@ __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// Wave reductions.  Each row of 16 lanes is scanned with DPP row shifts
+// (lane i combines lane i-1, i-2, i-4, i-8 of its row; lanes without a
+// source keep their value), so lane 15 of every row holds the row's result;
+// the four row results are then read as scalars and combined in a fixed
+// order.  Plain VALU work, no LDS round trips.  The whole wave must be
+// active; the result is uniform.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+
+template <int CTRL>
+__device__ inline int dpp_row(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xf, 0xf, false);
+}
+__device__ inline float rl_f(float v, int t) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t)); }
+__device__ inline int rl_i(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+__device__ inline int64_t rl_i64(int64_t v, int t)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, t);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), t);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ inline int dpp_row0(int v) // 0 where the row has no source lane
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ inline int64_t dpp_row_i64(int64_t v) // 0 where the row has no source lane
+{
+    const int lo = dpp_row0<CTRL>((int)(uint32_t)v);
+    const int hi = dpp_row0<CTRL>((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ inline int64_t wave_sum_i64(int64_t v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o);
-    return v;
+    v += dpp_row_i64<DPP_ROW_SHR1>(v);
+    v += dpp_row_i64<DPP_ROW_SHR2>(v);
+    v += dpp_row_i64<DPP_ROW_SHR4>(v);
+    v += dpp_row_i64<DPP_ROW_SHR8>(v);
+    return (rl_i64(v, 15) + rl_i64(v, 31)) + (rl_i64(v, 47) + rl_i64(v, 63));
 }
 __device__ inline int32_t wave_sum_i32(int32_t v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o);
-    return v;
+    v += dpp_row0<DPP_ROW_SHR1>(v);
+    v += dpp_row0<DPP_ROW_SHR2>(v);
+    v += dpp_row0<DPP_ROW_SHR4>(v);
+    v += dpp_row0<DPP_ROW_SHR8>(v);
+    return (rl_i(v, 15) + rl_i(v, 31)) + (rl_i(v, 47) + rl_i(v, 63));
 }
-__device__ inline double wave_sum_f64(double v)
+__device__ inline double wave_sum_f64(double v) // fixed order: deterministic
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o);
-    return v;
+    auto step = [](double x, auto ctrl) {
+        const int64_t b = dpp_row_i64<decltype(ctrl)::value>((int64_t)__double_as_longlong(x));
+        return x + __longlong_as_double((long long)b); // +0.0 where the row has no source lane
+    };
+    v = step(v, std::integral_constant<int, DPP_ROW_SHR1>());
+    v = step(v, std::integral_constant<int, DPP_ROW_SHR2>());
+    v = step(v, std::integral_constant<int, DPP_ROW_SHR4>());
+    v = step(v, std::integral_constant<int, DPP_ROW_SHR8>());
+    auto rl_d = [](double x, int t) { return __longlong_as_double((long long)rl_i64((int64_t)__double_as_longlong(x), t)); };
+    return (rl_d(v, 15) + rl_d(v, 31)) + (rl_d(v, 47) + rl_d(v, 63));
 }
 __device__ inline float wave_min_f32(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v = fminf(v, __shfl_xor(v, o));
-    return v;
+    v = fminf(v, __int_as_float(dpp_row<DPP_ROW_SHR1>(__float_as_int(v), __float_as_int(v))));
+    v = fminf(v, __int_as_float(dpp_row<DPP_ROW_SHR2>(__float_as_int(v), __float_as_int(v))));
+    v = fminf(v, __int_as_float(dpp_row<DPP_ROW_SHR4>(__float_as_int(v), __float_as_int(v))));
+    v = fminf(v, __int_as_float(dpp_row<DPP_ROW_SHR8>(__float_as_int(v), __float_as_int(v))));
+    return fminf(fminf(rl_f(v, 15), rl_f(v, 31)), fminf(rl_f(v, 47), rl_f(v, 63)));
 }
 
 // Exact per-cluster accumulation of one wave's points.  Lanes with valid set
@@ -358,7 +420,7 @@ __device__ inline void wave_accumulate(bool valid, int a, const int64_t (&hi)[D]
     uint64_t active = __ballot(valid);
     while (active) {
         int leader = __ffsll((unsigned long long)active) - 1;
-        int c = __shfl(a, leader);
+        int c = rl_i(a, leader);
         bool in = valid && a == c && ((active >> lane_id()) & 1ull);
         uint64_t grp = __ballot(in);
         int32_t n = __popcll(grp);
@@ -368,7 +430,7 @@ __device__ inline void wave_accumulate(bool valid, int a, const int64_t (&hi)[D]
             sh[i] = wave_sum_i64(in ? hi[i] : 0);
             sl[i] = wave_sum_i64(in ? lo[i] : 0);
         }
-        if (lane_id() == leader) {
+        if (lane_id() == leader) { // the sums are uniform; one lane adds them
             int64_t *ac = acc + (int64_t)c * D * 2;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -386,7 +448,7 @@ struct TreeArgs {
     float4 *cs;               // [k] fl32 centroids in tree order, w = centroid id bits
     float4 *node_lo, *node_hi; // [nnodes] level 0 (buckets) first
     int nlev;                 // levels, the last one is the root
-    int start;                // lowest level with at most 256 nodes
+    int start;                // lowest level with at most TREE_START_MAX nodes
     int64_t nnodes;
     int64_t lev_size[TREE_MAX_LEVELS];
     int64_t lev_off[TREE_MAX_LEVELS];
@@ -411,6 +473,7 @@ struct km_ctx {
     int f = 64;          // maximum leaf size
     int tile = 1024;     // brute-path LDS tile (centroids)
     int S = 0;           // fixed-point scale exponent
+    int fix64 = 0;       // every point's fixed-point coordinate fits FIX64_BITS bits
     ekm::Grid grid{};    // Morton grid over the data bounding box
     // A0: Morton-ordered points and leaves
     void *xs = nullptr;           // [d][n] float or double
@@ -427,8 +490,9 @@ struct km_ctx {
     int32_t *cval = nullptr, *cval2 = nullptr;
     ekm::TreeArgs tree{};
     float *cerr = nullptr;        // [1] bits of an FP32 upper bound on max_j ||c_j||
-    // groups of GROUP_LEAVES consecutive leaves
+    // groups: runs of at most GROUP_LEAVES consecutive leaves inside one group cell
     int64_t ngroups = 0;
+    int32_t *group_leaf = nullptr; // [ngroups+1] first leaf of each group
     float4 *group_box = nullptr;  // [ngroups][2]
     // A5: exact sums
     int64_t *acc = nullptr;       // [k][d][2]

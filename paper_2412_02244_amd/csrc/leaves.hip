@@ -236,15 +236,64 @@ __global__ void __launch_bounds__(256) k_leaf_info(const float *xs, int64_t n, c
     }
 }
 
+// ------------------------------------------------------------ wave groups
+// Leaves are grouped for the centroid-tree descent: a group is a run of at
+// most GROUP_LEAVES consecutive leaves inside one group cell, the largest
+// Morton cell holding at most GROUP_CELL_POINTS(f) points (the leaf rule at
+// a coarser threshold).  Group boxes then stay inside one compact cell; runs
+// of consecutive leaves across a Morton jump would give boxes spanning
+// distant regions.  Every group-cell cut is a leaf cut (the threshold is a
+// multiple of f), so cells are unions of whole leaves.
+
+// cs[l] = 1 iff leaf l starts a group cell.
+__global__ void __launch_bounds__(256) k_cell_starts(const uint32_t *pflag, const int32_t *leaf_start, int64_t L,
+                                                     uint32_t *cs)
+{
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < L)
+        cs[l] = pflag[leaf_start[l]];
+}
+
+// First leaf of each cell (cscan = exclusive scan of cs).
+__global__ void __launch_bounds__(256) k_cell_first(const uint32_t *cs, const uint32_t *cscan, int64_t L,
+                                                    int32_t *cell_first)
+{
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < L && cs[l])
+        cell_first[cscan[l]] = (int32_t)l;
+}
+
+// ws[l] = 1 iff leaf l starts a group: its rank in its cell is a multiple of GROUP_LEAVES.
+__global__ void __launch_bounds__(256) k_group_starts(const uint32_t *cs, const uint32_t *cscan,
+                                                      const int32_t *cell_first, int64_t L, uint32_t *ws)
+{
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L)
+        return;
+    const int64_t cell = (int64_t)cscan[l] + cs[l] - 1;
+    const int64_t rank = l - cell_first[cell];
+    ws[l] = (rank % GROUP_LEAVES) == 0 ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_group_first(const uint32_t *ws, const uint32_t *gscan, int64_t L,
+                                                     int32_t *group_leaf, int64_t ngroups)
+{
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < L && ws[l])
+        group_leaf[gscan[l]] = (int32_t)l;
+    if (l == 0)
+        group_leaf[ngroups] = (int32_t)L;
+}
+
 // One thread per group: union of its leaves' boxes.
-__global__ void __launch_bounds__(256) k_group_boxes(const float4 *leaf_box, int64_t L, int64_t ngroups,
-                                                     float4 *group_box)
+__global__ void __launch_bounds__(256) k_group_boxes(const float4 *leaf_box, const int32_t *group_leaf,
+                                                     int64_t ngroups, float4 *group_box)
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngroups)
         return;
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f), hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    for (int64_t l = g * GROUP_LEAVES; l < L && l < (g + 1) * GROUP_LEAVES; ++l) {
+    for (int64_t l = group_leaf[g]; l < group_leaf[g + 1]; ++l) {
         float4 a = leaf_box[2 * l], b = leaf_box[2 * l + 1];
         lo.x = fminf(lo.x, a.x);
         lo.y = fminf(lo.y, a.y);
@@ -305,6 +354,7 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         return KM_ERR_NOT_EXACT;
     }
     ctx->S = S;
+    ctx->fix64 = (h0.any_nonzero ? h0.emsb + 1 + S : 0) <= FIX64_BITS ? 1 : 0;
     for (int i = 0; i < D; ++i) {
         float lo = float_of_ord(h0.lo[i]), hi = float_of_ord(h0.hi[i]);
         ctx->grid.lo[i] = lo;
@@ -369,14 +419,56 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         }
         hipLaunchKernelGGL((k_leaf_info<D>), dim3(nblocks(L * WAVE, 256)), dim3(256), 0, st, (const float *)xs, n,
                            ctx->leaf_start, L, S, (float4 *)ctx->leaf_box, ctx->leaf_sum);
-        ctx->ngroups = (L + GROUP_LEAVES - 1) / GROUP_LEAVES;
-        ctx->group_box = ctx_alloc<float4>(ctx, 2 * ctx->ngroups);
-        if (!ctx->group_box) {
-            set_error("kmeans_init: device allocation failed");
-            return KM_ERR_OOM;
+        // wave groups (flag and scan are free again; the leaf-level arrays
+        // live in scan, which holds n >= 4L words once L <= n/4, else in a
+        // temporary)
+        hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n,
+                           group_cell_points(ctx->f), flag);
+        uint32_t *tmp = nullptr;
+        uint32_t *lw = scan;
+        if (4 * L > n) {
+            if (hipMalloc((void **)&tmp, (size_t)4 * L * sizeof(uint32_t)) != hipSuccess) {
+                set_error("kmeans_init: device allocation failed");
+                return KM_ERR_OOM;
+            }
+            lw = tmp;
         }
-        hipLaunchKernelGGL(k_group_boxes, dim3(nblocks(ctx->ngroups, 256)), dim3(256), 0, st,
-                           (const float4 *)ctx->leaf_box, L, ctx->ngroups, ctx->group_box);
+        uint32_t *cs = lw, *cscan = lw + L, *ws = lw + 2 * L, *gscan = lw + 3 * L;
+        int32_t *cell_first = (int32_t *)gscan; // used before gscan is written
+        hipLaunchKernelGGL(k_cell_starts, dim3(nblocks(L, 256)), dim3(256), 0, st, flag, ctx->leaf_start, L, cs);
+        bool ok = hip_ok(hipMemcpyAsync(cscan, cs, L * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy") &&
+                  hip_ok(exclusive_scan_u32(cscan, L, scan_tmp, st), "scan");
+        if (ok) {
+            hipLaunchKernelGGL(k_cell_first, dim3(nblocks(L, 256)), dim3(256), 0, st, cs, cscan, L, cell_first);
+            hipLaunchKernelGGL(k_group_starts, dim3(nblocks(L, 256)), dim3(256), 0, st, cs, cscan,
+                               (const int32_t *)cell_first, L, ws);
+            ok = hip_ok(hipMemcpyAsync(gscan, ws, L * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy") &&
+                 hip_ok(exclusive_scan_u32(gscan, L, scan_tmp, st), "scan") &&
+                 hip_ok(hipMemcpyAsync(&last[0], gscan + L - 1, 4, hipMemcpyDeviceToHost, st), "copy") &&
+                 hip_ok(hipMemcpyAsync(&last[1], ws + L - 1, 4, hipMemcpyDeviceToHost, st), "copy") &&
+                 hip_ok(hipStreamSynchronize(st), "sync");
+        }
+        if (ok) {
+            ctx->ngroups = (int64_t)last[0] + last[1];
+            ctx->group_leaf = ctx_alloc<int32_t>(ctx, ctx->ngroups + 1);
+            ctx->group_box = ctx_alloc<float4>(ctx, 2 * ctx->ngroups);
+            if (!ctx->group_leaf || !ctx->group_box) {
+                if (tmp)
+                    (void)hipFree(tmp);
+                set_error("kmeans_init: device allocation failed");
+                return KM_ERR_OOM;
+            }
+            hipLaunchKernelGGL(k_group_first, dim3(nblocks(L, 256)), dim3(256), 0, st, ws, gscan, L, ctx->group_leaf,
+                               ctx->ngroups);
+            hipLaunchKernelGGL(k_group_boxes, dim3(nblocks(ctx->ngroups, 256)), dim3(256), 0, st,
+                               (const float4 *)ctx->leaf_box, (const int32_t *)ctx->group_leaf, ctx->ngroups,
+                               ctx->group_box);
+            ok = hip_ok(hipStreamSynchronize(st), "sync");
+        }
+        if (tmp)
+            (void)hipFree(tmp);
+        if (!ok)
+            return KM_ERR_HIP;
     }
     // keep the sort scratch for the centroid sort of large k
     ctx->ckey = keys;

@@ -323,9 +323,9 @@ void tree_layout(int64_t k, TreeArgs &T)
         sz = (sz + 7) / 8;
     }
     T.nnodes = off;
-    // the descent starts at the lowest level small enough for one pass of a workgroup
+    // a descent starts at the lowest level small enough to evaluate every node
     T.start = T.nlev - 1;
-    while (T.start > 0 && T.lev_size[T.start - 1] <= 256)
+    while (T.start > 0 && T.lev_size[T.start - 1] <= TREE_START_MAX)
         --T.start;
 }
 
