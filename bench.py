@@ -6,7 +6,8 @@ uniform background, the shape of the paper's GPS trajectory data sets),
 k = 1000, centroids initialised from a seeded permutation.  One step = one
 Lloyd iteration (centroid tree, leaf candidates, assignment with FP64
 recheck, exact centroid update).  The timed region is K consecutive
-iterations 1..K of that run on a fresh context, inputs already on the GPU.
+iterations 1..K of that run (kmeans_run on a fresh context), inputs already
+on the GPU.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -14,6 +15,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,16 +43,37 @@ def algorithmic_bytes(phase: str, n: int, k: int, d: int, L: int) -> float:
 
 
 def time_steps(ekm, torch, ctx, c0t, steps: int) -> float:
-    """GPU milliseconds for `steps` iterations from c0t (events on the current stream)."""
-    bufs = [c0t.clone(), torch.empty_like(c0t)]
+    """GPU milliseconds for `steps` iterations from c0t (kmeans_run; events on
+    the current stream, which is the stream the library launches on)."""
+    c = c0t.clone()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for i in range(steps):
-        ekm.kmeans_step(ctx, bufs[i % 2], bufs[(i + 1) % 2])
+    ekm.kmeans_run(ctx, c, steps)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_geo2d_1e6_k1000_traffic.json")
+
+
+def assign_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2412_02244_amd", "csrc", "assign.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per assignment step from the committed counter summary, or
+    None if the assignment kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("assign_hip_sha256") != assign_source_hash():
+        return None
+    return t.get("bytes_per_step")
 
 
 def cpu_baseline(x, c0, target_s: float):
@@ -68,7 +91,47 @@ def cpu_baseline(x, c0, target_s: float):
                        f"{dt:.1f} s on the host)")
 
 
+def summarize_counters(fetch_csv: str, write_csv: str) -> dict:
+    """HBM bytes per assignment step from two rocprofv3 --pmc runs of
+    `bench.py --quick --copy-calib` (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch).  Each counter is scaled by what it reads for the 256 MiB
+    device copy in the same run (expected: 256 MiB fetched, 256 MiB
+    written)."""
+    import csv
+    import statistics
+
+    copy_bytes = float(256 << 20)
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        by = {}
+        for r in rows:
+            by.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return by
+
+    out = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        by = per_kernel(path, name)
+        copies = [max(v) for k, v in by.items() if "copyBuffer" in k or "copy" in k.lower() and "ekm" not in k]
+        calib = max(copies) / copy_bytes if copies else 1.0
+        waves = [v for k, v in by.items() if "k_assign_waves" in k]
+        heavy = [v for k, v in by.items() if "k_assign_heavy" in k]
+        w = statistics.median(waves[0]) if waves else 0.0
+        h = statistics.median(heavy[0]) if heavy else 0.0
+        out[name] = dict(assign_waves_bytes=w / calib, assign_heavy_bytes=h / calib, copy_scale=calib)
+    total = sum(v["assign_waves_bytes"] + v["assign_heavy_bytes"] for v in out.values())
+    res = dict(workload="geo2d hotspots n=1e6 d=2 k=1000", counters=out, bytes_per_step=total,
+               assign_hip_sha256=assign_source_hash())
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main() -> int:
+    if len(sys.argv) == 4 and sys.argv[1] == "--summarize-counters":
+        print(json.dumps(summarize_counters(sys.argv[2], sys.argv[3]), indent=1))
+        return 0
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -76,6 +139,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="indexed timing only (for profiler runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
@@ -141,9 +206,16 @@ def main() -> int:
     dominant = max(phase_us, key=phase_us.get)
     bytes_dom = algorithmic_bytes(dominant, n, k, d, L)
     achieved = bytes_dom / (phase_us[dominant] * 1e-6) / 1e9
+    kern = {"assign": "k_assign_waves + k_assign_heavy", "tree": "k_tree_small", "update": "k_finalize"}[dominant]
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dominant,
+                    frac=round(achieved / HBM_PEAK_GBS, 5),
+                    traffic=measured_traffic() if dominant == "assign" else None, kernel=kern,
                     kernel_us=round(phase_us[dominant], 2), algorithmic_bytes=bytes_dom)
+    if args.copy_calib:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     out = {}
     if not args.quick:

@@ -92,14 +92,14 @@ static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
     int64_t L = n;                        // leaves <= n
     b += (size_t)(L + 1) * 4;             // leaf_start
     if (cfg->algo == KM_INDEXED) {
-        b += (size_t)L * (32 + d * 16 + 4);            // leaf box, exact sums, previous whole-leaf cluster
+        b += (size_t)L * (32 + d * 16 + 4 + 4) + 4;    // leaf box, exact sums, previous cluster, deferred list
         b += (size_t)L * 36 + 4;                      // groups (at most one per leaf): boxes, first leaves
         TreeArgs T;
         tree_layout(k, T);
         b += (size_t)T.nnodes * 32 + (size_t)k * 16;  // node boxes, tree-ordered centroids
     }
     b += (size_t)k * (16 + 4 + d * 16 + 4); // c32, cval, acc, cnt
-    int64_t nblk = cfg->algo == KM_INDEXED ? L : (n + 255) / 256; // statistics rows: groups or blocks
+    int64_t nblk = cfg->algo == KM_INDEXED ? L + HEAVY_WAVES : (n + 255) / 256; // statistics rows
     b += (size_t)nblk * (NSTAT * 8 + 8);
     b += 4096;
     return b;
@@ -235,11 +235,15 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
         T.node_lo = ctx_alloc<float4>(ctx, T.nnodes);
         T.node_hi = ctx_alloc<float4>(ctx, T.nnodes);
         ctx->leaf_prev = ctx_alloc<int32_t>(ctx, L);
-        if (!T.cs || !T.node_lo || !T.node_hi || !ctx->leaf_prev) {
+        ctx->heavy = ctx_alloc<int32_t>(ctx, L);
+        ctx->heavy_cnt = ctx_alloc<int32_t>(ctx, 1);
+        if (!T.cs || !T.node_lo || !T.node_hi || !ctx->leaf_prev || !ctx->heavy || !ctx->heavy_cnt) {
             kmeans_destroy(ctx);
             return alloc_fail(nullptr);
         }
-        if (!hip_ok(hipMemsetAsync(ctx->leaf_prev, 0xff, L * sizeof(int32_t), st), "hipMemsetAsync")) {
+        if (!hip_ok(hipMemsetAsync(ctx->leaf_prev, 0xff, L * sizeof(int32_t), st), "hipMemsetAsync") ||
+            !hip_ok(hipMemsetAsync(ctx->heavy, 0, L * sizeof(int32_t), st), "hipMemsetAsync") ||
+            !hip_ok(hipMemsetAsync(ctx->heavy_cnt, 0, sizeof(int32_t), st), "hipMemsetAsync")) {
             kmeans_destroy(ctx);
             return KM_ERR_HIP;
         }

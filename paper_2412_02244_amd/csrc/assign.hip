@@ -19,8 +19,7 @@ namespace ekm {
 constexpr int ASSIGN_THREADS = 256;
 constexpr int G_WAVES = ASSIGN_THREADS / WAVE; // independent waves per workgroup
 constexpr int SW_CAP = 256;                    // per-wave candidate list (LDS)
-constexpr int FR_CH = 8;                       // descent entries per level: FR_CH chunks of 64
-constexpr int FR_CAP = FR_CH * WAVE;
+constexpr int FR_CAP = 1024;                   // descent entries per level
 constexpr int PAR_CAP = FR_CAP / TREE_BUCKET;  // kept parents per level
 static_assert(GROUP_LEAVES <= WAVE, "one lane holds one leaf of the group");
 static_assert(TREE_START_MAX <= FR_CAP, "the first descent level fits the per-lane entries");
@@ -39,6 +38,8 @@ struct AssignArgs {
     const float4 *leaf_box;
     const int64_t *leaf_sum;
     int32_t *leaf_prev;
+    int32_t *heavy;
+    int32_t *heavy_cnt;
     const int32_t *group_leaf;
     const float4 *group_box;
     int64_t ngroups;
@@ -78,6 +79,7 @@ struct BlockStats {
 struct WaveShared {
     float4 sc[SW_CAP];    // candidate list of the current box: fl32 coordinates, w = centroid id
     int par[2][PAR_CAP];  // kept nodes of the previous descent level
+    float fm[FR_CAP];     // min-distances of the current level's entries (lane-private slots)
 };
 
 // Orders this wave's LDS writes before its later LDS reads by other lanes
@@ -124,20 +126,57 @@ __device__ inline void stats_end(BlockStats &bs, const AssignArgs &A, const int6
     }
 }
 
-// One wave's counters (wave-uniform values) and per-lane SSE terms ->
-// partial row `row` (lanes 0..NSTAT-1 store).
-__device__ inline void wave_stats_end(const AssignArgs &A, const int64_t (&c)[NSTAT], double sse, int64_t row)
+// Statistics of one workgroup of independent waves: each wave adds its
+// (wave-uniform) counters to LDS with atomics and parks its SSE in its own
+// slot; the wave that arrives last writes the workgroup's row, summing the
+// SSE slots in wave order (deterministic).  Initialised before any wave
+// diverges (the kernel's single workgroup barrier).
+struct BlockCombine {
+    unsigned long long v[NSTAT];
+    double sse[G_WAVES];
+    int done;
+};
+
+__device__ inline void combine_init(BlockCombine &bc)
 {
+    if (threadIdx.x < NSTAT)
+        bc.v[threadIdx.x] = 0;
+    if (threadIdx.x < G_WAVES)
+        bc.sse[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0)
+        bc.done = 0;
+    __syncthreads();
+}
+
+__device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const int64_t (&c)[NSTAT], double sse,
+                                   int64_t row)
+{
+    const int lane = lane_id();
     int64_t mine = 0;
 #pragma unroll
     for (int q = 0; q < NSTAT; ++q)
-        if (lane_id() == q)
+        if (lane == q)
             mine = c[q];
     const double ws = A.want_sse ? wave_sum_f64(sse) : 0.0;
-    if (lane_id() < NSTAT)
-        A.stat_part[row * NSTAT + lane_id()] = mine;
-    if (lane_id() == 0)
-        A.sse_part[row] = ws;
+    if (lane < NSTAT && mine)
+        __hip_atomic_fetch_add(&bc.v[lane], (unsigned long long)mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (lane == 0)
+        bc.sse[threadIdx.x / WAVE] = ws;
+    int last = 0;
+    if (lane == 0)
+        last = __hip_atomic_fetch_add(&bc.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == G_WAVES - 1;
+    if (!rl_i(last, 0))
+        return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < NSTAT)
+        A.stat_part[row * NSTAT + lane] =
+            (int64_t)__hip_atomic_load(&bc.v[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (lane == 0) {
+        double s = 0.0;
+        for (int w = 0; w < G_WAVES; ++w)
+            s += bc.sse[w];
+        A.sse_part[row] = s;
+    }
 }
 
 // Number of lanes of the wave with `p` set (wave-uniform).
@@ -148,11 +187,13 @@ __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 // length, or -1 if a descent level or the list does not fit.  The whole
 // wave calls; the result is uniform.
 //
-// The descent starts at the lowest tree level with at most FR_CAP nodes and
-// evaluates every node there; each later level evaluates the children of
-// the nodes kept at the level above, and the last step the centroids of the
-// kept buckets.  U is the smallest box-to-node max-distance seen at any
-// level (a valid bound: every node holds a centroid).
+// The descent starts at the lowest tree level with at most TREE_START_MAX
+// nodes and evaluates every node there; each later level evaluates the
+// children of the nodes kept at the level above (at most FR_CAP entries),
+// and the last step the centroids of the kept buckets.  U is the smallest
+// box-to-node max-distance seen at any level (a valid bound: every node
+// holds a centroid).  Each lane keeps the min-distances of its entries in
+// its own LDS slots between the two passes of a level.
 template <int D>
 __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A, float e, WaveShared &sh)
 {
@@ -167,40 +208,33 @@ __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A
     while (true) {
         const int64_t off = T.lev_off[level], lsz = T.lev_size[level];
         const int F = np < 0 ? (int)lsz : np * TREE_BUCKET;
-        float mv[FR_CH];
-        int nv[FR_CH];
         float Ul = INFINITY;
-#pragma unroll
-        for (int c = 0; c < FR_CH; ++c) {
-            mv[c] = INFINITY;
-            nv[c] = -1;
-            const int i = c * WAVE + lane;
-            if (c * WAVE < F && i < F) {
-                const int64_t node = np < 0 ? i : (int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
-                if (node < lsz) {
-                    float nl[3], nh[3];
-                    f4_to(T.node_lo[off + node], nl);
-                    f4_to(T.node_hi[off + node], nh);
-                    mv[c] = bb_mind<D>(lo, hi, nl, nh);
-                    nv[c] = (int)node;
-                    Ul = fminf(Ul, bb_maxd<D>(lo, hi, nl, nh));
-                }
+#pragma unroll 4
+        for (int i = lane; i < F; i += WAVE) {
+            const int64_t node = np < 0 ? i : (int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
+            float m = INFINITY;
+            if (node < lsz) {
+                float nl[3], nh[3];
+                f4_to(T.node_lo[off + node], nl);
+                f4_to(T.node_hi[off + node], nh);
+                m = bb_mind<D>(lo, hi, nl, nh);
+                Ul = fminf(Ul, bb_maxd<D>(lo, hi, nl, nh));
             }
+            sh.fm[i] = m; // read back by this lane only
         }
         U = fminf(U, wave_min_f32(Ul));
         const float thr = prune_threshold(U, e);
         const int nxt = cur ^ 1;
         int cnt = 0;
-#pragma unroll
-        for (int c = 0; c < FR_CH; ++c) {
-            if (c * WAVE < F) {
-                const bool keep = nv[c] >= 0 && mv[c] <= thr;
-                const uint64_t mk = __ballot(keep);
-                const int pos = cnt + __popcll(mk & lt);
-                if (keep && pos < PAR_CAP)
-                    sh.par[nxt][pos] = nv[c];
-                cnt += __popcll(mk);
-            }
+        for (int i0 = 0; i0 < F; i0 += WAVE) {
+            const int i = i0 + lane;
+            const bool keep = i < F && sh.fm[i] <= thr;
+            const uint64_t mk = __ballot(keep);
+            const int pos = cnt + __popcll(mk & lt);
+            if (keep && pos < PAR_CAP)
+                sh.par[nxt][pos] =
+                    np < 0 ? i : sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
+            cnt += __popcll(mk);
         }
         if (cnt > PAR_CAP)
             return -1;
@@ -213,38 +247,30 @@ __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A
     }
     // centroids of the kept buckets
     const int F = np * TREE_BUCKET;
-    float mv[FR_CH];
-    float4 cv[FR_CH];
     float Ul = INFINITY;
-#pragma unroll
-    for (int c = 0; c < FR_CH; ++c) {
-        mv[c] = INFINITY;
-        cv[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const int i = c * WAVE + lane;
-        if (c * WAVE < F && i < F) {
-            const int64_t t = (int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
-            if (t < A.k) {
-                cv[c] = T.cs[t];
-                float cc[3];
-                f4_to(cv[c], cc);
-                mv[c] = box_mind<D>(lo, hi, cc);
-                Ul = fminf(Ul, box_maxd<D>(lo, hi, cc));
-            }
+#pragma unroll 4
+    for (int i = lane; i < F; i += WAVE) {
+        const int64_t t = (int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
+        float m = INFINITY;
+        if (t < A.k) {
+            float cc[3];
+            f4_to(T.cs[t], cc);
+            m = box_mind<D>(lo, hi, cc);
+            Ul = fminf(Ul, box_maxd<D>(lo, hi, cc));
         }
+        sh.fm[i] = m;
     }
     U = fminf(U, wave_min_f32(Ul));
     const float thr = prune_threshold(U, e);
     int cnt = 0;
-#pragma unroll
-    for (int c = 0; c < FR_CH; ++c) {
-        if (c * WAVE < F) {
-            const bool keep = mv[c] <= thr;
-            const uint64_t mk = __ballot(keep);
-            const int pos = cnt + __popcll(mk & lt);
-            if (keep && pos < SW_CAP)
-                sh.sc[pos] = cv[c];
-            cnt += __popcll(mk);
-        }
+    for (int i0 = 0; i0 < F; i0 += WAVE) {
+        const int i = i0 + lane;
+        const bool keep = i < F && sh.fm[i] <= thr;
+        const uint64_t mk = __ballot(keep);
+        const int pos = cnt + __popcll(mk & lt);
+        if (keep && pos < SW_CAP) // the entry was loaded by this lane a moment ago (cache hit)
+            sh.sc[pos] = T.cs[(int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET];
+        cnt += __popcll(mk);
     }
     wave_sync();
     return cnt > SW_CAP ? -1 : cnt;
@@ -305,7 +331,10 @@ __device__ inline int brute64_all(const double (&xd)[D], const AssignArgs &A)
 // FIX64_BITS bits, else the hi/lo parts), its count a ballot popcount.  The
 // last cluster gets the leaf's precomputed exact sum minus what the others
 // took.  The values are then split into the (hi, lo) accumulator form and
-// lanes 0..2D-1 (sums) and 2D (count) add them with integer atomics.
+// lanes 0..2D-1 (sums) and 2D (count) add them with integer atomics.  A
+// leaf spread over many clusters (crowded centroids) stops reducing after
+// ACC_ROUNDS clusters; its remaining points add their own values.
+constexpr int ACC_ROUNDS = 3;
 template <int D>
 __device__ inline void accumulate_leaf(bool valid, int a, const float (&x)[D], const int64_t *lsum,
                                        const AssignArgs &A)
@@ -328,7 +357,24 @@ __device__ inline void accumulate_leaf(bool valid, int a, const float (&x)[D], c
     for (int i = 0; i < D; ++i)
         took_hi[i] = took_lo[i] = 0;
     uint64_t active = __ballot(valid);
-    while (active) {
+    for (int round = 0; active; ++round) {
+        if (round == ACC_ROUNDS) {
+            if ((active >> lane) & 1ull) {
+                int64_t *ac = A.acc + (int64_t)a * D * 2;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    int64_t h = v0[i], l = v1[i];
+                    if (A.fix64) {
+                        h = v0[i] >> 32;
+                        l = v0[i] - (h << 32);
+                    }
+                    atomicAdd((unsigned long long *)&ac[2 * i], (unsigned long long)h);
+                    atomicAdd((unsigned long long *)&ac[2 * i + 1], (unsigned long long)l);
+                }
+                atomicAdd(&A.cnt[a], 1);
+            }
+            break;
+        }
         const int c = rl_i(a, __ffsll((unsigned long long)active) - 1);
         const bool in = valid && a == c;
         const uint64_t grp = __ballot(in);
@@ -409,6 +455,32 @@ __device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, fl
     return m;
 }
 
+// Running (best, second-best, best id) of an FP32 scan; best compares
+// (value, id) lexicographically, so equal values keep the lowest id.
+struct Best2 {
+    float s1, s2;
+    int id;
+};
+__device__ inline Best2 best2_init() { return Best2{INFINITY, INFINITY, 0x7fffffff}; }
+__device__ inline void best2_add(Best2 &b, float sv, int cid)
+{
+    const bool better = sv < b.s1 || (sv == b.s1 && cid < b.id);
+    b.s2 = better ? b.s1 : fminf(b.s2, sv);
+    b.s1 = better ? sv : b.s1;
+    b.id = better ? cid : b.id;
+}
+// Merge of two scans over disjoint candidate sets.
+__device__ inline Best2 best2_merge(const Best2 &a, const Best2 &b)
+{
+    const bool af = a.s1 < b.s1 || (a.s1 == b.s1 && a.id < b.id);
+    Best2 r;
+    r.s1 = af ? a.s1 : b.s1;
+    r.id = af ? a.id : b.id;
+    r.s2 = fminf(af ? b.s1 : a.s1, fminf(a.s2, b.s2));
+    return r;
+}
+constexpr int SCAN_ILP = 4; // independent scans interleaved over the candidates
+
 // FP32 scan of one point (one lane) against the leaf's candidates: the list
 // entries within `thr` of the leaf box, in chunks, each candidate broadcast
 // from the lane that holds it.  Lanes whose best-vs-second margin is below
@@ -423,8 +495,10 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
 {
     const int lane = lane_id();
     const int nch = (sn + WAVE - 1) / WAVE;
-    float s1 = INFINITY, s2 = INFINITY;
-    int id1 = 0x7fffffff;
+    Best2 bs[SCAN_ILP];
+#pragma unroll
+    for (int u = 0; u < SCAN_ILP; ++u)
+        bs[u] = best2_init();
     for (int c = 0; c < nch; ++c) {
         const int jl = c * WAVE + lane;
         const float4 c4 = list_entry(sh, jl, sn);
@@ -432,17 +506,23 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
         f4_to(c4, cl);
         uint64_t mk = __ballot(jl < sn && box_mind<D>(blo, bhi, cl) <= thr);
         while (mk) {
-            const int b = __ffsll((unsigned long long)mk) - 1;
-            mk &= mk - 1;
-            float cc[3] = {rl_f(c4.x, b), rl_f(c4.y, b), D == 3 ? rl_f(c4.z, b) : 0.0f};
-            const int cid = rl_i(__float_as_int(c4.w), b);
-            const float sv = sqdist32<D>(x, cc);
-            const bool better = sv < s1 || (sv == s1 && cid < id1);
-            s2 = better ? s1 : fminf(s2, sv);
-            s1 = better ? sv : s1;
-            id1 = better ? cid : id1;
+            // up to SCAN_ILP candidates per round, one per independent scan
+#pragma unroll
+            for (int u = 0; u < SCAN_ILP; ++u) {
+                if (mk) {
+                    const int b = __ffsll((unsigned long long)mk) - 1;
+                    mk &= mk - 1;
+                    float cc[3] = {rl_f(c4.x, b), rl_f(c4.y, b), D == 3 ? rl_f(c4.z, b) : 0.0f};
+                    best2_add(bs[u], sqdist32<D>(x, cc), rl_i(__float_as_int(c4.w), b));
+                }
+            }
         }
     }
+#pragma unroll
+    for (int u = 1; u < SCAN_ILP; ++u)
+        bs[0] = best2_merge(bs[0], bs[u]);
+    const float s1 = bs[0].s1, s2 = bs[0].s2;
+    const int id1 = bs[0].id;
     const bool re = valid && !margin_safe(s1, s2, e);
     const int nre = wave_count(re);
     if (nre == 0)
@@ -451,7 +531,7 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
     double xd[D];
     for (int i = 0; i < D; ++i)
         xd[i] = (double)x[i];
-    const float hi1 = dist_hi(s1, e);
+    const float s_cap = lo_inverse(dist_hi(s1, e), e); // dist_lo(s) <= dist_hi(s1) implies s <= s_cap
     double bd = INFINITY;
     int bj = 0x7fffffff;
     for (int c = 0; c < nch; ++c) {
@@ -459,14 +539,22 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
         const float4 c4 = list_entry(sh, jl, sn);
         float cl[3];
         f4_to(c4, cl);
-        uint64_t mk = __ballot(jl < sn && box_mind<D>(blo, bhi, cl) <= thr);
+        const bool kc = jl < sn && box_mind<D>(blo, bhi, cl) <= thr;
+        double cdl[3] = {0.0, 0.0, 0.0}; // this lane's FP64 centroid, broadcast below
+        if (kc)
+            for (int i = 0; i < D; ++i)
+                cdl[i] = A.c_in[(int64_t)__float_as_int(c4.w) * D + i];
+        uint64_t mk = __ballot(kc);
         while (mk) {
             const int b = __ffsll((unsigned long long)mk) - 1;
             mk &= mk - 1;
             float cc[3] = {rl_f(c4.x, b), rl_f(c4.y, b), D == 3 ? rl_f(c4.z, b) : 0.0f};
             const int cid = rl_i(__float_as_int(c4.w), b);
-            if (re && dist_lo(sqdist32<D>(x, cc), e) <= hi1) {
-                const double Dv = sqdist64<D>(xd, A.c_in + (int64_t)cid * D);
+            double cd[D];
+            for (int i = 0; i < D; ++i)
+                cd[i] = rl_d(cdl[i], b);
+            if (re && sqdist32<D>(x, cc) <= s_cap) {
+                const double Dv = sqdist64<D>(xd, cd);
                 if (Dv < bd || (Dv == bd && cid < bj)) {
                     bd = Dv;
                     bj = cid;
@@ -514,21 +602,34 @@ __device__ void process_leaf_all(int64_t l, int s, int size, int prev, const Ass
     float x[D];
     for (int i = 0; i < D; ++i)
         x[i] = valid ? xs[(int64_t)i * A.n + p] : 0.0f;
-    float s1 = INFINITY, s2 = INFINITY;
-    int id1 = 0;
-    for (int64_t j = 0; j < A.k; ++j) {
-        float cc[3];
-        f4_to(A.c32[j], cc);
-        float sv = sqdist32<D>(x, cc);
-        if (sv < s1) {
-            s2 = s1;
-            s1 = sv;
-            id1 = (int)j;
-        } else {
-            s2 = fminf(s2, sv);
+    // all k centroids, 64 at a time in registers (the next chunk loading
+    // while this one is scanned), ascending j: strict < keeps the lowest index
+    Best2 bs[SCAN_ILP];
+#pragma unroll
+    for (int u = 0; u < SCAN_ILP; ++u)
+        bs[u] = best2_init();
+    float4 cur = lane < A.k ? A.c32[lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int64_t j0 = 0; j0 < A.k; j0 += WAVE) {
+        const int64_t jn = j0 + WAVE + lane;
+        const float4 nxt = jn < A.k ? A.c32[jn] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const int cn = (int)(A.k - j0 < WAVE ? A.k - j0 : WAVE);
+        for (int b0 = 0; b0 < cn; b0 += SCAN_ILP) {
+#pragma unroll
+            for (int u = 0; u < SCAN_ILP; ++u) {
+                const int b = b0 + u;
+                if (b < cn) {
+                    float cc[3] = {rl_f(cur.x, b), rl_f(cur.y, b), D == 3 ? rl_f(cur.z, b) : 0.0f};
+                    best2_add(bs[u], sqdist32<D>(x, cc), (int)(j0 + b));
+                }
+            }
         }
+        cur = nxt;
     }
-    int best = id1;
+#pragma unroll
+    for (int u = 1; u < SCAN_ILP; ++u)
+        bs[0] = best2_merge(bs[0], bs[u]);
+    const float s1 = bs[0].s1, s2 = bs[0].s2;
+    int best = bs[0].id;
     const bool re = valid && !margin_safe(s1, s2, e);
     if (re) {
         double xd[D];
@@ -561,14 +662,11 @@ __device__ inline void leaf_of(const LeafRegs &r, int t, float *blo, float *bhi)
 
 // One leaf against the wave's list (the per-leaf path: no prefetch).
 template <int D>
-__device__ void process_leaf(int64_t l, const LeafRegs &r, int t, int sn, const AssignArgs &A, float e,
-                             const WaveShared &sh, int64_t (&st)[NSTAT], double &sse)
+__device__ void process_leaf(int64_t l, int s, int size, int prev, const float *blo, const float *bhi, int sn,
+                             const AssignArgs &A, float e, const WaveShared &sh, int64_t (&st)[NSTAT], double &sse)
 {
     const int lane = lane_id();
     const float *xs = (const float *)A.xs;
-    const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
-    float blo[3], bhi[3];
-    leaf_of<D>(r, t, blo, bhi);
     float thr;
     int j1;
     const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
@@ -601,8 +699,8 @@ __device__ inline void load_leaf(const LeafRegs &r, int t, int m, int j1, const 
     const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
     const int64_t p = (int64_t)s + lane;
     const bool valid = lane < size;
-    const bool need_x = m != 1 || A.want_sse;
-    const bool need_a = m != 1 || prev != j1;
+    const bool need_x = m <= HEAVY_M && (m != 1 || A.want_sse);
+    const bool need_a = m <= HEAVY_M && (m != 1 || prev != j1);
     av = -1;
     for (int i = 0; i < D; ++i)
         xv[i] = 0.0f;
@@ -635,17 +733,27 @@ __device__ inline void load_leaf(const LeafRegs &r, int t, int m, int j1, const 
 // If S does not fit, the wave searches leaf by leaf, and a leaf whose own
 // list does not fit scans all k centroids; results are the same.
 template <int D>
+__device__ void group_work(int64_t g, const AssignArgs &A, WaveShared &sh, int64_t (&st)[NSTAT], double &sse);
+
+template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
 {
     __shared__ WaveShared wsh[G_WAVES];
-    const int lane = lane_id();
+    __shared__ BlockCombine bc;
+    combine_init(bc);
     const int64_t g = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
-    if (g >= A.ngroups)
-        return; // whole wave; nothing below synchronises across waves
-    WaveShared &sh = wsh[threadIdx.x / WAVE];
-    const float e = err_bound(A.cmax_bits);
     int64_t st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
     double sse = 0.0;
+    if (g < A.ngroups) // whole wave; nothing in group_work synchronises across waves
+        group_work<D>(g, A, wsh[threadIdx.x / WAVE], st, sse);
+    combine_end(bc, A, st, sse, blockIdx.x);
+}
+
+template <int D>
+__device__ void group_work(int64_t g, const AssignArgs &A, WaveShared &sh, int64_t (&st)[NSTAT], double &sse)
+{
+    const int lane = lane_id();
+    const float e = err_bound(A.cmax_bits);
     const int64_t l0 = A.group_leaf[g];
     const int nl = A.group_leaf[g + 1] - (int)l0; // 1..GROUP_LEAVES
     LeafRegs r;
@@ -672,11 +780,11 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
             leaf_of<D>(r, t, blo, bhi);
             const int ln = wave_search<D>(blo, bhi, A, e, sh);
             if (ln >= 0)
-                process_leaf<D>(l0 + t, r, t, ln, A, e, sh, st, sse);
+                process_leaf<D>(l0 + t, rl_i(r.start, t), rl_i(r.size, t), rl_i(r.prev, t), blo, bhi, ln, A, e, sh,
+                                st, sse);
             else
                 process_leaf_all<D>(l0 + t, rl_i(r.start, t), rl_i(r.size, t), rl_i(r.prev, t), A, e, st, sse);
         }
-        wave_stats_end(A, st, sse, g);
         return;
     }
     // filter every leaf first; lane t keeps leaf t's results
@@ -712,6 +820,13 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
         const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
         const int64_t p = (int64_t)s + lane;
         const bool valid = lane < size;
+        if (m > HEAVY_M) { // a wave of its own in the per-leaf pass
+            if (lane == 0) {
+                A.heavy[l] = 1;
+                atomicAdd(A.heavy_cnt, 1);
+            }
+            continue;
+        }
         st[ST_CANDS] += m;
         if (m == 1) {
             const int j = j1;
@@ -753,7 +868,50 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
         st[ST_EVALS] += (int64_t)m * size;
         leaf_finish<D>(A, l, valid, p, x, best, aold, st, sse);
     }
-    wave_stats_end(A, st, sse, g);
+}
+
+// k_assign_heavy: the leaves k_assign_waves flagged as deferred (more than
+// HEAVY_M candidates), each with its own tree search for the leaf box, then
+// the point-by-point scan.  Such leaves sit where many centroids crowd
+// near a large sparse cell; spreading them over waves keeps one group from
+// serialising several of them.  Wave w takes leaves w, w + nw, w + 2nw, ...
+// in increasing order, so which wave sums which leaf (and the FP64 SSE
+// rounding) does not depend on timing; it clears the flags it consumed.
+template <int D>
+__global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
+{
+    __shared__ WaveShared wsh[G_WAVES];
+    __shared__ BlockCombine bc;
+    combine_init(bc);
+    WaveShared &sh = wsh[threadIdx.x / WAVE];
+    const int64_t w = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * G_WAVES;
+    const float e = err_bound(A.cmax_bits);
+    int64_t st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double sse = 0.0;
+    if (uniform_int(*A.heavy_cnt) > 0) {
+        for (int64_t base = w; base < A.L; base += nw * WAVE) {
+            const int64_t lf = base + (int64_t)lane_id() * nw;
+            uint64_t mk = __ballot(lf < A.L && A.heavy[lf] != 0);
+            while (mk) {
+                const int b = __ffsll((unsigned long long)mk) - 1;
+                mk &= mk - 1;
+                const int64_t l = base + (int64_t)b * nw;
+                const int s = A.leaf_start[l], size = A.leaf_start[l + 1] - s, prev = A.leaf_prev[l];
+                float blo[3], bhi[3];
+                f4_to(A.leaf_box[2 * l], blo);
+                f4_to(A.leaf_box[2 * l + 1], bhi);
+                const int ln = wave_search<D>(blo, bhi, A, e, sh);
+                if (ln >= 0)
+                    process_leaf<D>(l, s, size, prev, blo, bhi, ln, A, e, sh, st, sse);
+                else
+                    process_leaf_all<D>(l, s, size, prev, A, e, st, sse);
+                if (lane_id() == 0)
+                    A.heavy[l] = 0;
+            }
+        }
+    }
+    combine_end(bc, A, st, sse, (A.ngroups + G_WAVES - 1) / G_WAVES + blockIdx.x);
 }
 
 // ------------------------------------------------------------- brute force
@@ -862,6 +1020,8 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
     A.leaf_box = (const float4 *)ctx->leaf_box;
     A.leaf_sum = ctx->leaf_sum;
     A.leaf_prev = ctx->leaf_prev;
+    A.heavy = ctx->heavy;
+    A.heavy_cnt = ctx->heavy_cnt;
     A.group_leaf = ctx->group_leaf;
     A.group_box = ctx->group_box;
     A.ngroups = ctx->ngroups;
@@ -881,7 +1041,7 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
 int64_t assign_blocks(const km_ctx *ctx)
 {
     if (ctx->cfg.algo == KM_INDEXED)
-        return ctx->ngroups;
+        return (ctx->ngroups + G_WAVES - 1) / G_WAVES + HEAVY_WAVES / G_WAVES;
     return (ctx->n + ASSIGN_THREADS - 1) / ASSIGN_THREADS;
 }
 
@@ -893,10 +1053,14 @@ km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse)
     const unsigned nwg = (unsigned)((ctx->ngroups + G_WAVES - 1) / G_WAVES);
     const int D = ctx->d;
     if (ctx->cfg.algo == KM_INDEXED) {
-        if (D == 2)
+        const unsigned nhw = HEAVY_WAVES / G_WAVES;
+        if (D == 2) {
             hipLaunchKernelGGL(k_assign_waves<2>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
-        else
+            hipLaunchKernelGGL(k_assign_heavy<2>, dim3(nhw), dim3(ASSIGN_THREADS), 0, st, A);
+        } else {
             hipLaunchKernelGGL(k_assign_waves<3>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
+            hipLaunchKernelGGL(k_assign_heavy<3>, dim3(nhw), dim3(ASSIGN_THREADS), 0, st, A);
+        }
     } else if (ctx->cfg.point_dtype == KM_F32) {
         size_t lds = (size_t)ctx->tile * sizeof(float4);
         if (D == 2)

@@ -18,6 +18,8 @@ namespace ekm {
 constexpr int WAVE = 64;
 constexpr int MAX_LEAF = 64;     // a leaf fits one wave
 constexpr int GROUP_LEAVES = 8;  // consecutive leaves sharing one centroid-tree descent (one wave)
+constexpr int HEAVY_M = 24;      // leaves with more candidates get a wave of their own
+constexpr int HEAVY_WAVES = 1024; // waves of the per-leaf pass (one statistics row each)
 // Group cells: the largest Morton cells with at most this many points (a
 // multiple of the leaf size, so cells are unions of whole leaves).
 inline constexpr int group_cell_points(int f) { return 8 * f; }
@@ -105,6 +107,14 @@ constexpr float TAU = 0x1p-120f;
 __device__ inline float dist_hi(float s, float e) { return sqrtf(s + TAU) * MARGIN_UP + e; }
 // Lower bound on sqrt(D64) given FP32 s.
 __device__ inline float dist_lo(float s, float e) { return sqrtf(fmaxf(s - TAU, 0.0f)) * MARGIN_DN - e; }
+
+// A bound T on FP32 squared distances with: dist_lo(s, e) <= h implies
+// s <= T (T is loose on purpose; it only has to keep every such s).
+__device__ inline float lo_inverse(float h, float e)
+{
+    const float r = (h + e) * MARGIN_UP * MARGIN_UP;
+    return r * r * MARGIN_UP + TAU;
+}
 
 // True when the FP32 best (s1) is certainly the FP64 argmin against every
 // centroid whose FP32 value is >= s2.
@@ -356,6 +366,10 @@ __device__ inline int64_t rl_i64(int64_t v, int t)
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), t);
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+__device__ inline double rl_d(double v, int t)
+{
+    return __longlong_as_double((long long)rl_i64((int64_t)__double_as_longlong(v), t));
+}
 
 template <int CTRL>
 __device__ inline int dpp_row0(int v) // 0 where the row has no source lane
@@ -484,6 +498,8 @@ struct km_ctx {
     float *leaf_box = nullptr;    // [L][2][4] lo xyz pad, hi xyz pad
     int64_t *leaf_sum = nullptr;  // [L][d][2] exact fixed-point sums
     int32_t *leaf_prev = nullptr; // [L] whole-leaf cluster of the previous step, or -1
+    int32_t *heavy = nullptr;     // [L] 1 for leaves deferred to the per-leaf pass of this step
+    int32_t *heavy_cnt = nullptr; // [1] their number (reset by the finalize kernel)
     // A1: centroid tree
     float4 *c32 = nullptr;        // [k] fl32(c) in caller order
     uint32_t *ckey = nullptr, *ckey2 = nullptr;

@@ -19,7 +19,8 @@ template <int D>
 __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, double *c_out, int64_t k, int64_t *acc,
                                                           int32_t *cnt, int S, int64_t nblk, const int64_t *stat_part,
                                                           const double *sse_part, int64_t *stat_out, double *sse_out,
-                                                          unsigned *cmax_bits, int64_t nclusterblocks)
+                                                          unsigned *cmax_bits, int32_t *heavy_cnt,
+                                                          int64_t nclusterblocks)
 {
     if ((int64_t)blockIdx.x < nclusterblocks) {
         int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,6 +82,8 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, do
     if (threadIdx.x == 0) {
         *sse_out = dred[0];
         *cmax_bits = 0u; // the next centroid tree recomputes the norm bound
+        if (heavy_cnt)
+            *heavy_cnt = 0; // the deferred-leaf list of the next step starts empty
     }
 }
 
@@ -102,11 +105,11 @@ km_status run_finalize(km_ctx *ctx, const double *c_in, double *c_out, int32_t *
     if (ctx->d == 2)
         hipLaunchKernelGGL(k_finalize<2>, dim3((unsigned)(ncb + 1)), dim3(FIN_THREADS), 0, st, c_in, c_out, ctx->k,
                            ctx->acc, ctx->cnt, ctx->S, nblk, ctx->stat_part, ctx->sse_part, ctx->stat_out,
-                           ctx->sse_out, (unsigned *)ctx->cerr, ncb);
+                           ctx->sse_out, (unsigned *)ctx->cerr, ctx->heavy_cnt, ncb);
     else
         hipLaunchKernelGGL(k_finalize<3>, dim3((unsigned)(ncb + 1)), dim3(FIN_THREADS), 0, st, c_in, c_out, ctx->k,
                            ctx->acc, ctx->cnt, ctx->S, nblk, ctx->stat_part, ctx->sse_part, ctx->stat_out,
-                           ctx->sse_out, (unsigned *)ctx->cerr, ncb);
+                           ctx->sse_out, (unsigned *)ctx->cerr, ctx->heavy_cnt, ncb);
     if (!hip_ok(hipGetLastError(), "finalize launch"))
         return KM_ERR_HIP;
     return assign_out ? scatter_assignment(ctx, assign_out) : KM_OK;

@@ -16,7 +16,7 @@
 
 namespace ekm {
 
-constexpr int SMALL_K = 8192;
+constexpr int SMALL_K = 4096;
 constexpr int TREE_THREADS = 1024;
 constexpr int TREE_WAVES = TREE_THREADS / WAVE;
 
@@ -66,14 +66,16 @@ __device__ inline float centroid_prep_one(const double *c, int64_t j, const Grid
 }
 
 // ------------------------------------------------------------------ small k
-// Everything in one workgroup: prep, stable LSD radix sort (8-bit digits) of
-// the top 16 key bits in LDS, tree-ordered copy, all node boxes.
+// Everything in one workgroup, LDS-resident after one read of the centroids:
+// prep, stable LSD radix sort (8-bit digits) of the top 16 key bits, the
+// tree-ordered copy and every node box; global memory is only written.
 template <int D>
 __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, int64_t k, Grid g, TreeArgs T,
                                                              float4 *c32, unsigned *cmax_bits)
 {
     extern __shared__ unsigned char smem[];
-    uint32_t *key = (uint32_t *)smem;         // [SMALL_K]
+    float4 *cq = (float4 *)smem;              // [SMALL_K] fl32 centroids, caller order
+    uint32_t *key = (uint32_t *)(cq + SMALL_K); // [SMALL_K]
     uint32_t *id = key + SMALL_K;             // [SMALL_K]
     uint32_t *key2 = id + SMALL_K;            // [SMALL_K]
     uint32_t *id2 = key2 + SMALL_K;           // [SMALL_K]
@@ -88,6 +90,7 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, in
         float4 q4;
         uint32_t kb;
         nb = fmaxf(nb, centroid_prep_one<D>(c, j, g, q4, kb));
+        cq[j] = q4;
         c32[j] = q4;
         key[j] = kb >> shift;
         id[j] = (uint32_t)j;
@@ -170,37 +173,41 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, in
             __syncthreads();
         }
     }
-    // sorted ids are back in `id`
+    // sorted ids are back in `id`; node boxes go to LDS (over key2/id2,
+    // free now: at most 2 * SMALL_K / TREE_BUCKET float4 pairs) and out
+    float4 *nlo = (float4 *)key2, *nhi = nlo + T.nnodes;
     for (int t = tid; t < kk; t += TREE_THREADS) {
         int cid = (int)id[t];
-        float4 p = c32[cid];
+        float4 p = cq[cid];
         p.w = __int_as_float(cid);
         T.cs[t] = p;
     }
-    // level 0: buckets
-    const int64_t nb0 = T.lev_size[0];
-    for (int64_t b = tid; b < nb0; b += TREE_THREADS) {
+    const int nb0 = (int)T.lev_size[0];
+    for (int b = tid; b < nb0; b += TREE_THREADS) {
         float4 lo, hi;
         box_empty(lo, hi);
-        for (int64_t t = b * TREE_BUCKET; t < k && t < (b + 1) * TREE_BUCKET; ++t)
-            box_add(lo, hi, c32[id[t]]);
+        const int te = (b + 1) * TREE_BUCKET < kk ? (b + 1) * TREE_BUCKET : kk;
+        for (int t = b * TREE_BUCKET; t < te; ++t)
+            box_add(lo, hi, cq[id[t]]);
+        nlo[b] = lo;
+        nhi[b] = hi;
         T.node_lo[b] = lo;
         T.node_hi[b] = hi;
     }
-    // device-scope fence: the next level reads boxes other threads wrote
-    __threadfence();
     __syncthreads();
     for (int l = 1; l < T.nlev; ++l) {
-        const int64_t off = T.lev_off[l], poff = T.lev_off[l - 1], psz = T.lev_size[l - 1];
-        for (int64_t i = tid; i < T.lev_size[l]; i += TREE_THREADS) {
+        const int off = (int)T.lev_off[l], poff = (int)T.lev_off[l - 1], psz = (int)T.lev_size[l - 1];
+        for (int i = tid; i < (int)T.lev_size[l]; i += TREE_THREADS) {
             float4 lo, hi;
             box_empty(lo, hi);
-            for (int64_t ch = 8 * i; ch < 8 * i + 8 && ch < psz; ++ch)
-                box_union(lo, hi, T.node_lo[poff + ch], T.node_hi[poff + ch]);
+            const int ce = 8 * i + 8 < psz ? 8 * i + 8 : psz;
+            for (int ch = 8 * i; ch < ce; ++ch)
+                box_union(lo, hi, nlo[poff + ch], nhi[poff + ch]);
+            nlo[off + i] = lo;
+            nhi[off + i] = hi;
             T.node_lo[off + i] = lo;
             T.node_hi[off + i] = hi;
         }
-        __threadfence();
         __syncthreads();
     }
 }
@@ -259,7 +266,13 @@ __global__ void __launch_bounds__(256) k_tree_level(TreeArgs T, int l)
     T.node_hi[off + i] = hi;
 }
 
-static size_t small_tree_lds() { return (size_t)SMALL_K * 16 + (size_t)TREE_WAVES * 256 * 4 + 256 * 4; }
+static size_t small_tree_lds()
+{
+    return (size_t)SMALL_K * 16 + (size_t)SMALL_K * 16 + (size_t)TREE_WAVES * 256 * 4 + 256 * 4;
+}
+// The node boxes of a k <= SMALL_K tree fit in the key2/id2 region.
+static_assert(2 * (SMALL_K / TREE_BUCKET + SMALL_K / TREE_BUCKET / 7 + 8) * 16 <= SMALL_K * 8,
+              "node boxes of the small tree fit in LDS");
 
 km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
 {
