@@ -146,6 +146,40 @@ def test_ties_on_bisector_go_to_lowest_index(ekm):
         assert (got[0][0][:257] == 0).all()
 
 
+@pytest.fixture(scope="module")
+def surfaces_1e7():
+    x, _, _ = make_config(2)
+    return x
+
+
+@pytest.mark.parametrize("k", [10_000, 100_000])
+def test_full_size_surfaces3d_sampled(ekm, surfaces_1e7, k):
+    """1e7 x 3D ellipsoid surfaces, k = 1e4 (LDS tree build) and 1e5 (global
+    radix tree build): two steps; sampled assignments against the oracle's
+    brute force, every centroid against the oracle's exact update of the
+    GPU's own assignment."""
+    import torch
+    x = surfaces_1e7
+    c0 = init_centroids(x, k, 2002)  # the seed make_config(2) uses
+    dev = torch.device("cuda:0")
+    _say(f"[parity] surfaces3d n={x.shape[0]} k={k}: context")
+    ctx = ekm.kmeans_init(torch.from_numpy(x).to(dev), k, algo=ekm.KM_INDEXED)
+    rng = np.random.default_rng(k)
+    sample = np.concatenate([rng.choice(x.shape[0], 5000, replace=False), np.arange(64), [x.shape[0] - 1]])
+    c = torch.from_numpy(c0).to(dev)
+    a = torch.empty(x.shape[0], dtype=torch.int32, device=dev)
+    for t in range(2):
+        _say(f"[parity] surfaces3d k={k} step {t + 1}")
+        c_prev = c.cpu().numpy()
+        c = ekm.kmeans_step(ctx, c, assign_out=a)
+        a_gpu = a.cpu().numpy()
+        a_ref, _ = oracle.assign(x[sample], c_prev)
+        assert (a_gpu[sample] == a_ref).all(), f"step {t + 1}: sampled assignments differ from the oracle"
+        c_ref, _ = oracle.update(x, a_gpu, c_prev)
+        np.testing.assert_array_equal(c.cpu().numpy(), c_ref)
+    ctx.close()
+
+
 def test_full_size_geo2d_stepwise(ekm):
     """1e6 x 2D, k=1000 (the benchmark workload): each step's sampled
     assignments against the oracle's brute force, the whole update against
