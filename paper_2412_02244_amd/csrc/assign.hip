@@ -455,28 +455,31 @@ __device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, fl
     return m;
 }
 
-// Running (best, second-best, best id) of an FP32 scan; best compares
-// (value, id) lexicographically, so equal values keep the lowest id.
+// Running (best, second-best, best id) of an FP32 scan.  The best is kept
+// as one 64-bit key (value bits << 32 | id): squared distances are >= 0, so
+// their bit patterns order like the values, and one unsigned compare gives
+// the (value, id) order with the lowest id first among equal values.
 struct Best2 {
-    float s1, s2;
-    int id;
+    uint64_t key;
+    float s2;
 };
-__device__ inline Best2 best2_init() { return Best2{INFINITY, INFINITY, 0x7fffffff}; }
+__device__ inline Best2 best2_init() { return Best2{~0ull, INFINITY}; }
+__device__ inline float best2_s1(const Best2 &b) { return __uint_as_float((uint32_t)(b.key >> 32)); }
+__device__ inline int best2_id(const Best2 &b) { return (int)(uint32_t)b.key; }
 __device__ inline void best2_add(Best2 &b, float sv, int cid)
 {
-    const bool better = sv < b.s1 || (sv == b.s1 && cid < b.id);
-    b.s2 = better ? b.s1 : fminf(b.s2, sv);
-    b.s1 = better ? sv : b.s1;
-    b.id = better ? cid : b.id;
+    const uint64_t k = ((uint64_t)__float_as_uint(sv) << 32) | (uint32_t)cid;
+    const bool better = k < b.key;
+    b.s2 = fminf(b.s2, better ? best2_s1(b) : sv); // the loser of the two
+    b.key = better ? k : b.key;
 }
 // Merge of two scans over disjoint candidate sets.
 __device__ inline Best2 best2_merge(const Best2 &a, const Best2 &b)
 {
-    const bool af = a.s1 < b.s1 || (a.s1 == b.s1 && a.id < b.id);
+    const bool af = a.key < b.key;
     Best2 r;
-    r.s1 = af ? a.s1 : b.s1;
-    r.id = af ? a.id : b.id;
-    r.s2 = fminf(af ? b.s1 : a.s1, fminf(a.s2, b.s2));
+    r.key = af ? a.key : b.key;
+    r.s2 = fminf(best2_s1(af ? b : a), fminf(a.s2, b.s2));
     return r;
 }
 constexpr int SCAN_ILP = 4; // independent scans interleaved over the candidates
@@ -521,8 +524,8 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
 #pragma unroll
     for (int u = 1; u < SCAN_ILP; ++u)
         bs[0] = best2_merge(bs[0], bs[u]);
-    const float s1 = bs[0].s1, s2 = bs[0].s2;
-    const int id1 = bs[0].id;
+    const float s1 = best2_s1(bs[0]), s2 = bs[0].s2;
+    const int id1 = best2_id(bs[0]);
     const bool re = valid && !margin_safe(s1, s2, e);
     const int nre = wave_count(re);
     if (nre == 0)
@@ -628,8 +631,8 @@ __device__ void process_leaf_all(int64_t l, int s, int size, int prev, const Ass
 #pragma unroll
     for (int u = 1; u < SCAN_ILP; ++u)
         bs[0] = best2_merge(bs[0], bs[u]);
-    const float s1 = bs[0].s1, s2 = bs[0].s2;
-    int best = bs[0].id;
+    const float s1 = best2_s1(bs[0]), s2 = bs[0].s2;
+    int best = best2_id(bs[0]);
     const bool re = valid && !margin_safe(s1, s2, e);
     if (re) {
         double xd[D];
