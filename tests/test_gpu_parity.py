@@ -282,3 +282,28 @@ def test_distortion_fwd_bwd(ekm, dtype):
     tol = 1e-6 if dtype == "f32" else 1e-12
     np.testing.assert_allclose(xt.grad.cpu().numpy(), gx_ref, rtol=tol, atol=tol * np.abs(gx_ref).max())
     np.testing.assert_allclose(ct.grad.cpu().numpy(), gc_ref, rtol=tol, atol=tol * np.abs(gc_ref).max())
+
+
+def test_distortion_full_batch_sampled_clouds(ekm):
+    """The distortion pair at its full batch shape (256 clouds x 16,384 3D
+    points, k = 512, one launch each way): four clouds, including the first
+    and the last, checked against the oracle (assignments bit-exact, loss
+    1e-12 relative, gradients at the FP32 output tolerance)."""
+    import torch
+    from synth import distortion_batch
+    xb, cb = distortion_batch()
+    dev = torch.device("cuda:0")
+    xt = torch.from_numpy(xb).to(dev)
+    ct = torch.from_numpy(cb).to(dev)
+    _say(f"[parity] distortion full batch B={xb.shape[0]} n={xb.shape[1]} k={cb.shape[1]}")
+    a_gpu, loss = ekm.distortion_fwd(xt, ct)
+    g = torch.linspace(0.5, 1.5, xb.shape[0], dtype=torch.float64, device=dev)
+    gx, gc = ekm.distortion_bwd(xt, ct, a_gpu, g)
+    a_gpu, loss, gx, gc = a_gpu.cpu().numpy(), loss.cpu().numpy(), gx.cpu().numpy(), gc.cpu().numpy()
+    pick = np.array([0, 77, 190, xb.shape[0] - 1])
+    a_ref, l_ref = oracle.distortion_fwd(xb[pick], cb[pick])
+    assert (a_gpu[pick] == a_ref).all()
+    np.testing.assert_allclose(loss[pick], l_ref, rtol=1e-12)
+    gx_ref, gc_ref = oracle.distortion_bwd(xb[pick], cb[pick], a_ref, g.cpu().numpy()[pick])
+    np.testing.assert_allclose(gx[pick], gx_ref, rtol=1e-6, atol=1e-6 * np.abs(gx_ref).max())
+    np.testing.assert_allclose(gc[pick], gc_ref, rtol=1e-6, atol=1e-6 * np.abs(gc_ref).max())
