@@ -139,6 +139,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="indexed timing only (for profiler runs)")
+    ap.add_argument("--workload", choices=["geo2d", "surfaces3d"], default="geo2d",
+                    help="geo2d: 1e6 x 2D, k=1000 (the metric); surfaces3d: 1e7 x 3D ellipsoid surfaces")
+    ap.add_argument("--k", type=int, default=0, help="surfaces3d: number of centroids (default 10000)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -154,7 +157,10 @@ def main() -> int:
 
     ekm.load_library()
     dev = torch.device("cuda:0")
-    x, c0, cfg = make_config(1)
+    if args.workload == "geo2d":
+        x, c0, cfg = make_config(1)
+    else:
+        x, c0, cfg = make_config(2, k=args.k or 10_000)
     n, d = x.shape
     k = c0.shape[0]
     K, W = args.steps, args.warmup
@@ -209,7 +215,8 @@ def main() -> int:
     kern = {"assign": "k_assign_waves + k_assign_heavy", "tree": "k_tree_small", "update": "k_finalize"}[dominant]
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5),
-                    traffic=measured_traffic() if dominant == "assign" else None, kernel=kern,
+                    traffic=measured_traffic() if dominant == "assign" and args.workload == "geo2d" else None,
+                    kernel=kern,
                     kernel_us=round(phase_us[dominant], 2), algorithmic_bytes=bytes_dom)
     if args.copy_calib:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
@@ -231,13 +238,14 @@ def main() -> int:
                                 speedup_indexed=round(bms / ms_per_step, 2))
         log(f"brute GPU: {bms * 1e3:.1f} us/iteration; indexed speedup {bms / ms_per_step:.1f}x")
     cpu = None
-    if not args.no_cpu_baseline and not args.quick:
+    if not args.no_cpu_baseline and not args.quick and args.workload == "geo2d":
         log("CPU oracle baseline ...")
         cpu = cpu_baseline(x, c0, args.cpu_seconds)
         log(f"oracle: {cpu['value']:.3e} point-assignments/s on {cpu['cores']} threads")
 
     line = {
-        "metric": METRIC,
+        "metric": METRIC if args.workload == "geo2d" else
+        f"point-assignments/s per Lloyd iter, 1e7x3D ellipsoid surfaces k={k}; indexed vs brute GPU",
         "value": value,
         "unit": "point-assignments/s",
         "n_gpus": 1,
@@ -249,8 +257,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "geo2d hotspots, n=1e6, d=2, k=1000, indexed FP32 + FP64 recheck, "
-                               f"Lloyd iterations 1..{K}",
+        "config": {"workload": (f"geo2d hotspots, n=1e6, d=2, k=1000" if args.workload == "geo2d" else
+                                f"ellipsoid surfaces, n=1e7, d=3, k={k}") +
+                               f", indexed FP32 + FP64 recheck, Lloyd iterations 1..{K}",
                    "n": n, "d": d, "k": k, "global_batch": n, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

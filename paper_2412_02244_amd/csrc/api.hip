@@ -99,7 +99,7 @@ static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
         b += (size_t)T.nnodes * 32 + (size_t)k * 16;  // node boxes, tree-ordered centroids
     }
     b += (size_t)k * (16 + 4 + d * 16 + 4); // c32, cval, acc, cnt
-    int64_t nblk = cfg->algo == KM_INDEXED ? L + HEAVY_WAVES : (n + 255) / 256; // statistics rows
+    int64_t nblk = cfg->algo == KM_INDEXED ? L + heavy_waves(L) : (n + 255) / 256; // statistics rows
     b += (size_t)nblk * (NSTAT * 8 + 8);
     b += 4096;
     return b;

@@ -18,11 +18,14 @@ namespace ekm {
 
 constexpr int ASSIGN_THREADS = 256;
 constexpr int G_WAVES = ASSIGN_THREADS / WAVE; // independent waves per workgroup
-constexpr int SW_CAP = 256;                    // per-wave candidate list (LDS)
-constexpr int FR_CAP = 1024;                   // descent entries per level
-constexpr int PAR_CAP = FR_CAP / TREE_BUCKET;  // kept parents per level
+// Per-wave LDS capacities: candidate list entries and descent entries per
+// level.  A leaf whose list does not fit in the main pass goes to the
+// per-leaf pass, whose waves have room for crowded leaves (one workgroup
+// per CU there).
+constexpr int SW_MAIN = 256, FR_MAIN = 1024;
+constexpr int SW_HEAVY = 1024, FR_HEAVY = 4096;
 static_assert(GROUP_LEAVES <= WAVE, "one lane holds one leaf of the group");
-static_assert(TREE_START_MAX <= FR_CAP, "the first descent level fits the per-lane entries");
+static_assert(TREE_START_MAX <= FR_MAIN && TREE_START_MAX <= FR_HEAVY, "the first descent level fits");
 static_assert(MAX_LEAF <= WAVE, "one lane holds one point of a leaf");
 
 struct AssignArgs {
@@ -76,11 +79,15 @@ struct BlockStats {
 
 // Per-wave LDS of the indexed kernel.  Only lanes of the owning wave touch
 // it; writes by some lanes are read by others only after wave_sync().
-struct WaveShared {
-    float4 sc[SW_CAP];    // candidate list of the current box: fl32 coordinates, w = centroid id
-    int par[2][PAR_CAP];  // kept nodes of the previous descent level
-    float fm[FR_CAP];     // min-distances of the current level's entries (lane-private slots)
+template <int SW, int FR>
+struct WaveSharedT {
+    static constexpr int sw = SW, fr = FR, npar = FR / TREE_BUCKET;
+    float4 sc[SW];        // candidate list of the current box: fl32 coordinates, w = centroid id
+    int par[2][npar];     // kept nodes of the previous descent level
+    float fm[FR];         // min-distances of the current level's entries (lane-private slots)
 };
+using WaveMain = WaveSharedT<SW_MAIN, FR_MAIN>;
+using WaveHeavy = WaveSharedT<SW_HEAVY, FR_HEAVY>;
 
 // Orders this wave's LDS writes before its later LDS reads by other lanes
 // (the LDS executes one wave's operations in issue order; the fences keep
@@ -194,8 +201,8 @@ __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 // box-to-node max-distance seen at any level (a valid bound: every node
 // holds a centroid).  Each lane keeps the min-distances of its entries in
 // its own LDS slots between the two passes of a level.
-template <int D>
-__device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A, float e, WaveShared &sh)
+template <int D, class WS>
+__device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A, float e, WS &sh)
 {
     const TreeArgs &T = A.T;
     const int lane = lane_id();
@@ -231,12 +238,12 @@ __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A
             const bool keep = i < F && sh.fm[i] <= thr;
             const uint64_t mk = __ballot(keep);
             const int pos = cnt + __popcll(mk & lt);
-            if (keep && pos < PAR_CAP)
+            if (keep && pos < WS::npar)
                 sh.par[nxt][pos] =
                     np < 0 ? i : sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
             cnt += __popcll(mk);
         }
-        if (cnt > PAR_CAP)
+        if (cnt > WS::npar)
             return -1;
         wave_sync();
         np = cnt;
@@ -268,12 +275,12 @@ __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A
         const bool keep = i < F && sh.fm[i] <= thr;
         const uint64_t mk = __ballot(keep);
         const int pos = cnt + __popcll(mk & lt);
-        if (keep && pos < SW_CAP) // the entry was loaded by this lane a moment ago (cache hit)
+        if (keep && pos < WS::sw) // the entry was loaded by this lane a moment ago (cache hit)
             sh.sc[pos] = T.cs[(int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET];
         cnt += __popcll(mk);
     }
     wave_sync();
-    return cnt > SW_CAP ? -1 : cnt;
+    return cnt > WS::sw ? -1 : cnt;
 }
 
 // --------------------------------------------------------------- epilogue
@@ -415,7 +422,8 @@ __device__ inline void accumulate_leaf(bool valid, int a, const float (&x)[D], c
 // The wave's list is read in chunks of 64 entries, lane j holding entry
 // 64c + j in registers; a candidate is then broadcast to all lanes with
 // readlane (scalar operands, no LDS round trip per candidate).
-__device__ inline float4 list_entry(const WaveShared &sh, int j, int sn)
+template <class WS>
+__device__ inline float4 list_entry(const WS &sh, int j, int sn)
 {
     return j < sn ? sh.sc[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
@@ -423,8 +431,8 @@ __device__ inline float4 list_entry(const WaveShared &sh, int j, int sn)
 // Candidate filter of one leaf box against the wave's list (sn entries):
 // returns the candidate count m, the id of the first candidate (the only
 // one when m == 1) and the threshold for the later mask passes.
-template <int D>
-__device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, float e, const WaveShared &sh,
+template <int D, class WS>
+__device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, float e, const WS &sh,
                                   float &thr, int &j1)
 {
     const int lane = lane_id();
@@ -491,9 +499,9 @@ constexpr int SCAN_ILP = 4; // independent scans interleaved over the candidates
 // candidates that can still be nearest: those whose FP32 lower bound does
 // not exceed the best one's upper bound (any other is strictly farther in
 // exact and in FP64 arithmetic).  Returns the centroid id.
-template <int D>
+template <int D, class WS>
 __device__ inline int assign_point(const float (&x)[D], bool valid, const float *blo, const float *bhi, float thr,
-                                   int sn, float e, const AssignArgs &A, const WaveShared &sh,
+                                   int sn, float e, const AssignArgs &A, const WS &sh,
                                    int64_t (&st)[NSTAT])
 {
     const int lane = lane_id();
@@ -664,9 +672,9 @@ __device__ inline void leaf_of(const LeafRegs &r, int t, float *blo, float *bhi)
 }
 
 // One leaf against the wave's list (the per-leaf path: no prefetch).
-template <int D>
+template <int D, class WS>
 __device__ void process_leaf(int64_t l, int s, int size, int prev, const float *blo, const float *bhi, int sn,
-                             const AssignArgs &A, float e, const WaveShared &sh, int64_t (&st)[NSTAT], double &sse)
+                             const AssignArgs &A, float e, const WS &sh, int64_t (&st)[NSTAT], double &sse)
 {
     const int lane = lane_id();
     const float *xs = (const float *)A.xs;
@@ -736,12 +744,12 @@ __device__ inline void load_leaf(const LeafRegs &r, int t, int m, int j1, const 
 // If S does not fit, the wave searches leaf by leaf, and a leaf whose own
 // list does not fit scans all k centroids; results are the same.
 template <int D>
-__device__ void group_work(int64_t g, const AssignArgs &A, WaveShared &sh, int64_t (&st)[NSTAT], double &sse);
+__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t (&st)[NSTAT], double &sse);
 
 template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
 {
-    __shared__ WaveShared wsh[G_WAVES];
+    __shared__ WaveMain wsh[G_WAVES];
     __shared__ BlockCombine bc;
     combine_init(bc);
     const int64_t g = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
@@ -753,7 +761,7 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
 }
 
 template <int D>
-__device__ void group_work(int64_t g, const AssignArgs &A, WaveShared &sh, int64_t (&st)[NSTAT], double &sse)
+__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t (&st)[NSTAT], double &sse)
 {
     const int lane = lane_id();
     const float e = err_bound(A.cmax_bits);
@@ -782,11 +790,13 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveShared &sh, int64
             float blo[3], bhi[3];
             leaf_of<D>(r, t, blo, bhi);
             const int ln = wave_search<D>(blo, bhi, A, e, sh);
-            if (ln >= 0)
+            if (ln >= 0) {
                 process_leaf<D>(l0 + t, rl_i(r.start, t), rl_i(r.size, t), rl_i(r.prev, t), blo, bhi, ln, A, e, sh,
                                 st, sse);
-            else
-                process_leaf_all<D>(l0 + t, rl_i(r.start, t), rl_i(r.size, t), rl_i(r.prev, t), A, e, st, sse);
+            } else if (lane == 0) { // the per-leaf pass has room for it
+                A.heavy[l0 + t] = 1;
+                atomicAdd(A.heavy_cnt, 1);
+            }
         }
         return;
     }
@@ -883,10 +893,10 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveShared &sh, int64
 template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
 {
-    __shared__ WaveShared wsh[G_WAVES];
+    __shared__ WaveHeavy wsh[G_WAVES];
     __shared__ BlockCombine bc;
     combine_init(bc);
-    WaveShared &sh = wsh[threadIdx.x / WAVE];
+    WaveHeavy &sh = wsh[threadIdx.x / WAVE];
     const int64_t w = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
     const int64_t nw = (int64_t)gridDim.x * G_WAVES;
     const float e = err_bound(A.cmax_bits);
@@ -1044,7 +1054,7 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
 int64_t assign_blocks(const km_ctx *ctx)
 {
     if (ctx->cfg.algo == KM_INDEXED)
-        return (ctx->ngroups + G_WAVES - 1) / G_WAVES + HEAVY_WAVES / G_WAVES;
+        return (ctx->ngroups + G_WAVES - 1) / G_WAVES + heavy_waves(ctx->L) / G_WAVES;
     return (ctx->n + ASSIGN_THREADS - 1) / ASSIGN_THREADS;
 }
 
@@ -1056,7 +1066,7 @@ km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse)
     const unsigned nwg = (unsigned)((ctx->ngroups + G_WAVES - 1) / G_WAVES);
     const int D = ctx->d;
     if (ctx->cfg.algo == KM_INDEXED) {
-        const unsigned nhw = HEAVY_WAVES / G_WAVES;
+        const unsigned nhw = (unsigned)(heavy_waves(ctx->L) / G_WAVES);
         if (D == 2) {
             hipLaunchKernelGGL(k_assign_waves<2>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
             hipLaunchKernelGGL(k_assign_heavy<2>, dim3(nhw), dim3(ASSIGN_THREADS), 0, st, A);

@@ -19,7 +19,14 @@ constexpr int WAVE = 64;
 constexpr int MAX_LEAF = 64;     // a leaf fits one wave
 constexpr int GROUP_LEAVES = 8;  // consecutive leaves sharing one centroid-tree descent (one wave)
 constexpr int HEAVY_M = 24;      // leaves with more candidates get a wave of their own
-constexpr int HEAVY_WAVES = 1024; // waves of the per-leaf pass (one statistics row each)
+// Waves of the per-leaf pass: L/16, at least 1024, at most 65536 (a multiple
+// of 4: four waves share one statistics row).
+inline int64_t heavy_waves(int64_t L)
+{
+    int64_t w = L / 16;
+    w = w < 1024 ? 1024 : (w > 65536 ? 65536 : w);
+    return (w + 3) / 4 * 4;
+}
 // Group cells: the largest Morton cells with at most this many points (a
 // multiple of the leaf size, so cells are unions of whole leaves).
 inline constexpr int group_cell_points(int f) { return 8 * f; }
