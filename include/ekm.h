@@ -162,11 +162,18 @@ EKM_API km_status distortion_fwd(const void *x, const void *c, int32_t dtype, in
                          int64_t k, int32_t d, int32_t *assign_out, double *loss_out, void *stream);
 
 /* Gradient of sum_b g_b L_b with the assignment held fixed (it is piecewise
- * constant in x and c):
+ * constant in x and c; Eq. (1) differentiated cluster by cluster):
  *   grad_x[b,i] = 2 g_b (x_i - c_a(i))
- *   grad_c[b,j] = 2 g_b sum_{i in S_j} (c_j - x_i)   (accumulated in FP64)
+ *   grad_c[b,j] = 2 g_b RN(sum_{i in S_j} (c_j - x_i))   (the sum is exact)
  *   assign: device, B x n int32 from distortion_fwd; grad_loss: device, B FP64.
- *   grad_x / grad_c: device, same shape and dtype as x / c, or NULL to skip. */
+ *   grad_x / grad_c: device, same shape and dtype as x / c, or NULL to skip.
+ * Fully stream-ordered: the call never waits for the GPU.  grad_c's exact
+ * sums use a fixed-point window found on the device; scratch for them is a
+ * stream-ordered allocation (hipMallocAsync / hipFreeAsync on `stream`).  If
+ * the coordinates span more than 94 bits of fixed point (values of wildly
+ * different binary magnitudes), grad_c is filled with NaN instead.
+ * Errors: KM_ERR_INVALID (null x, c, assign or grad_loss; sizes < 1; d not
+ * 2/3; B > 65535), KM_ERR_OOM (scratch allocation), KM_ERR_HIP. */
 EKM_API km_status distortion_bwd(const void *x, const void *c, const int32_t *assign,
                          const double *grad_loss, int32_t dtype, int64_t B, int64_t n, int64_t k,
                          int32_t d, void *grad_x, void *grad_c, void *stream);

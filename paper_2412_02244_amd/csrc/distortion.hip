@@ -135,16 +135,36 @@ __global__ void __launch_bounds__(DT_THREADS) k_dist_gx(const T *x, const T *c, 
     }
 }
 
+// Exact-sum window of the gradient's cluster sums: every coordinate of x and
+// c is an integer multiple of 2^-S, S = the largest -(exponent of a lowest set
+// bit); the sums need emsb + 1 + S + log2(n) bits.  Computed on the device, so
+// the backward pass never waits for the host.
 struct WinOut {
-    int32_t neg_elsb, emsb, any;
+    int32_t neg_elsb, emsb, any, status; // status: 0 = ok, 1 = the window is too wide
 };
 
+// Clears the accumulators and the window (a fill kernel, not a memset, so
+// that the call can be captured into a graph).
+__global__ void __launch_bounds__(DT_THREADS) k_dist_zero(int64_t *acc, int64_t nacc, int32_t *cnt, int64_t ncnt,
+                                                          WinOut *win)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nacc; q += stride)
+        acc[q] = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ncnt; q += stride)
+        cnt[q] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *win = WinOut{-100000, -100000, 0, 0};
+}
+
 template <class T>
-__global__ void __launch_bounds__(DT_THREADS) k_dist_window(const T *v, int64_t m, WinOut *out)
+__global__ void __launch_bounds__(DT_THREADS) k_dist_window(const T *v, int64_t m, const T *w, int64_t mw,
+                                                            WinOut *out)
 {
     int ne = -100000, em = -100000, any = 0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x) {
-        T t = v[q];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m + mw; q += stride) {
+        T t = q < m ? v[q] : w[q - m];
         if (t != (T)0) {
             int el, eh;
             if (sizeof(T) == 4)
@@ -163,10 +183,21 @@ __global__ void __launch_bounds__(DT_THREADS) k_dist_window(const T *v, int64_t 
     }
 }
 
-template <class T, int D>
-__global__ void __launch_bounds__(DT_THREADS) k_dist_acc(const T *x, const int32_t *a, int64_t n, int64_t k, int S,
-                                                         int64_t *acc, int32_t *cnt)
+// Window checks, identical in every thread that reads the window: the sums
+// need emsb + 1 + S + log2(n) bits, and the product cnt * c_j 31 more.
+__device__ inline bool window_ok(const WinOut &w, int logn, int &S)
 {
+    S = w.any ? w.neg_elsb : 0;
+    return !w.any || (w.emsb + 1 + S + logn <= MAX_FIX_BITS && w.emsb + 1 + S + 31 <= 125);
+}
+
+template <class T, int D>
+__global__ void __launch_bounds__(DT_THREADS) k_dist_acc(const T *x, const int32_t *a, int64_t n, int64_t k,
+                                                         const WinOut *win, int logn, int64_t *acc, int32_t *cnt)
+{
+    int S;
+    if (!window_ok(*win, logn, S))
+        return; // k_dist_gc reports it
     const int64_t b = blockIdx.y;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = p < n;
@@ -183,16 +214,25 @@ __global__ void __launch_bounds__(DT_THREADS) k_dist_acc(const T *x, const int32
 }
 
 template <class T, int D>
-__global__ void __launch_bounds__(DT_THREADS) k_dist_gc(const T *c, const double *g, int64_t B, int64_t k, int S,
-                                                        const int64_t *acc, const int32_t *cnt, T *gc)
+__global__ void __launch_bounds__(DT_THREADS) k_dist_gc(const T *c, const double *g, int64_t B, int64_t k,
+                                                        WinOut *win, int logn, const int64_t *acc,
+                                                        const int32_t *cnt, T *gc)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= B * k)
         return;
+    int S;
+    const bool ok = window_ok(*win, logn, S);
+    if (!ok && q == 0)
+        win->status = 1;
     int64_t b = q / k;
     double two_g = 2.0 * g[b];
     int32_t m = cnt[q];
     for (int i = 0; i < D; ++i) {
+        if (!ok) { // no exact sum is possible: the gradient is marked invalid
+            gc[q * D + i] = (T)NAN;
+            continue;
+        }
         int64_t ch, cl;
         T cv = c[q * D + i];
         if (sizeof(T) == 4)
@@ -237,9 +277,17 @@ static km_status fwd_t(const T *x, const T *c, int64_t B, int64_t n, int64_t k, 
     return hip_ok(hipGetLastError(), "distortion_fwd launch") ? KM_OK : KM_ERR_HIP;
 }
 
+// Scratch of the centroid-gradient sums: [B][k][D][2] int64, [B][k] int32,
+// one window record.
+size_t dist_scratch_bytes(int64_t B, int64_t k, int d)
+{
+    return ((size_t)B * k * d * 2 * sizeof(int64_t) + (size_t)B * k * sizeof(int32_t) + 255) / 256 * 256 +
+           256;
+}
+
 template <class T, int D>
 static km_status bwd_t(const T *x, const T *c, const int32_t *a, const double *g, int64_t B, int64_t n, int64_t k,
-                       T *gx, T *gc, hipStream_t st)
+                       T *gx, T *gc, void *scratch, hipStream_t st)
 {
     if (gx) {
         int64_t tot = B * n;
@@ -250,47 +298,43 @@ static km_status bwd_t(const T *x, const T *c, const int32_t *a, const double *g
     }
     if (!gc)
         return KM_OK;
-    // exact-sum window over x and c (one small host round trip)
-    size_t acc_bytes = (size_t)B * k * D * 2 * sizeof(int64_t), cnt_bytes = (size_t)B * k * sizeof(int32_t);
-    char *buf = nullptr;
-    if (!hip_ok(hipMallocAsync((void **)&buf, acc_bytes + cnt_bytes + 256, st), "distortion_bwd: hipMallocAsync"))
-        return KM_ERR_OOM;
+    const size_t acc_bytes = (size_t)B * k * D * 2 * sizeof(int64_t);
+    const size_t cnt_bytes = (size_t)B * k * sizeof(int32_t);
+    char *buf = (char *)scratch;
     int64_t *acc = (int64_t *)buf;
     int32_t *cnt = (int32_t *)(buf + acc_bytes);
-    WinOut *win = (WinOut *)(buf + acc_bytes + cnt_bytes + 128 - ((acc_bytes + cnt_bytes) % 128));
-    WinOut h = {-100000, -100000, 0};
-    km_status status = KM_OK;
-    if (!hip_ok(hipMemcpyAsync(win, &h, sizeof(h), hipMemcpyHostToDevice, st), "distortion_bwd: copy") ||
-        !hip_ok(hipMemsetAsync(buf, 0, acc_bytes + cnt_bytes, st), "distortion_bwd: memset"))
-        status = KM_ERR_HIP;
-    if (status == KM_OK) {
-        hipLaunchKernelGGL(k_dist_window<T>, dim3(1024), dim3(DT_THREADS), 0, st, x, B * n * D, win);
-        hipLaunchKernelGGL(k_dist_window<T>, dim3(256), dim3(DT_THREADS), 0, st, c, B * k * D, win);
-        if (!hip_ok(hipMemcpyAsync(&h, win, sizeof(h), hipMemcpyDeviceToHost, st), "distortion_bwd: copy") ||
-            !hip_ok(hipStreamSynchronize(st), "distortion_bwd: sync"))
-            status = KM_ERR_HIP;
-    }
-    if (status == KM_OK) {
-        int S = h.any ? h.neg_elsb : 0;
-        int logn = 0;
-        while (((int64_t)1 << logn) < n)
-            ++logn;
-        // sums need emsb+1+S+log2(n) bits; the product cnt * c_j adds 31 bits
-        if (h.any && (h.emsb + 1 + S + logn > MAX_FIX_BITS || h.emsb + 1 + S + 31 > 125)) {
-            set_error("distortion_bwd: coordinates span too many bits for exact centroid sums");
-            status = KM_ERR_NOT_EXACT;
-        } else {
-            dim3 grid((unsigned)((n + DT_THREADS - 1) / DT_THREADS), (unsigned)B);
-            hipLaunchKernelGGL((k_dist_acc<T, D>), grid, dim3(DT_THREADS), 0, st, x, a, n, k, S, acc, cnt);
-            int64_t tot = B * k;
-            hipLaunchKernelGGL((k_dist_gc<T, D>), dim3((unsigned)((tot + DT_THREADS - 1) / DT_THREADS)),
-                               dim3(DT_THREADS), 0, st, c, g, B, k, S, acc, cnt, gc);
-            if (!hip_ok(hipGetLastError(), "distortion_bwd launch"))
-                status = KM_ERR_HIP;
-        }
-    }
-    hipFreeAsync(buf, st);
-    return status;
+    WinOut *win = (WinOut *)(buf + (acc_bytes + cnt_bytes + 255) / 256 * 256);
+    int logn = 0;
+    while (((int64_t)1 << logn) < n)
+        ++logn;
+    const int64_t nacc = B * k * D * 2, ncnt = B * k;
+    unsigned zb = (unsigned)((nacc + DT_THREADS - 1) / DT_THREADS);
+    zb = zb < 1 ? 1 : (zb > 4096 ? 4096 : zb);
+    hipLaunchKernelGGL(k_dist_zero, dim3(zb), dim3(DT_THREADS), 0, st, acc, nacc, cnt, ncnt, win);
+    hipLaunchKernelGGL(k_dist_window<T>, dim3(1024), dim3(DT_THREADS), 0, st, x, B * n * D, c, B * k * D, win);
+    dim3 grid((unsigned)((n + DT_THREADS - 1) / DT_THREADS), (unsigned)B);
+    hipLaunchKernelGGL((k_dist_acc<T, D>), grid, dim3(DT_THREADS), 0, st, x, a, n, k, (const WinOut *)win, logn, acc,
+                       cnt);
+    const int64_t tot = B * k;
+    hipLaunchKernelGGL((k_dist_gc<T, D>), dim3((unsigned)((tot + DT_THREADS - 1) / DT_THREADS)), dim3(DT_THREADS), 0,
+                       st, c, g, B, k, win, logn, (const int64_t *)acc, (const int32_t *)cnt, gc);
+    return hip_ok(hipGetLastError(), "distortion_bwd launch") ? KM_OK : KM_ERR_HIP;
+}
+
+template <class T, int D>
+static km_status bwd_alloc(const T *x, const T *c, const int32_t *a, const double *g, int64_t B, int64_t n,
+                           int64_t k, T *gx, T *gc, hipStream_t st)
+{
+    if (!gc)
+        return bwd_t<T, D>(x, c, a, g, B, n, k, gx, gc, nullptr, st);
+    // stream-ordered scratch: no host synchronisation
+    void *buf = nullptr;
+    if (!hip_ok(hipMallocAsync(&buf, dist_scratch_bytes(B, k, D), st), "distortion_bwd: hipMallocAsync"))
+        return KM_ERR_OOM;
+    km_status s = bwd_t<T, D>(x, c, a, g, B, n, k, gx, gc, buf, st);
+    if (!hip_ok(hipFreeAsync(buf, st), "distortion_bwd: hipFreeAsync") && s == KM_OK)
+        s = KM_ERR_HIP;
+    return s;
 }
 
 } // namespace ekm
@@ -327,14 +371,14 @@ km_status distortion_bwd(const void *x, const void *c, const int32_t *assign, co
     }
     hipStream_t st = (hipStream_t)stream;
     if (dtype == KM_F32)
-        return d == 2 ? bwd_t<float, 2>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
-                                        (float *)grad_x, (float *)grad_c, st)
-                      : bwd_t<float, 3>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
-                                        (float *)grad_x, (float *)grad_c, st);
-    return d == 2 ? bwd_t<double, 2>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
-                                     (double *)grad_x, (double *)grad_c, st)
-                  : bwd_t<double, 3>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
-                                     (double *)grad_x, (double *)grad_c, st);
+        return d == 2 ? bwd_alloc<float, 2>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
+                                            (float *)grad_x, (float *)grad_c, st)
+                      : bwd_alloc<float, 3>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
+                                            (float *)grad_x, (float *)grad_c, st);
+    return d == 2 ? bwd_alloc<double, 2>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
+                                         (double *)grad_x, (double *)grad_c, st)
+                  : bwd_alloc<double, 3>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
+                                         (double *)grad_x, (double *)grad_c, st);
 }
 
 } // extern "C"

@@ -90,9 +90,45 @@ def test_assign_matches_brute_force_tiny():
             a, dm = oracle.assign(x, c)
             np.testing.assert_array_equal(a, _brute_argmin(x, c))
             # the distance reported is the one to the chosen centroid (3D: all dims used)
-            ref = np.array([sum((float(x[i, t]) - float(c[a[i], t])) ** 2 for t in range(d))
-                            for i in range(n)])
-            np.testing.assert_allclose(dm, ref, rtol=1e-15, atol=0)
+            def canon(p, q):
+                s = 0.0
+                for t in range(d):
+                    u = float(p[t]) - float(q[t])
+                    s = s + u * u  # each operation rounded once, left to right
+                return s
+            ref = np.array([canon(x[i], c[a[i]]) for i in range(n)])
+            np.testing.assert_array_equal(dm, ref)  # bitwise: the canonical rounding, no FMA
+
+
+def _fma(a, b, c):
+    """fl(a*b + c) with one rounding (exact rational arithmetic)."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def test_distance_is_not_contracted_into_fma():
+    """Hand cases where fl(fl(dx^2) + fl(dy^2)) and fma(dx, dx, fl(dy^2))
+    order two centroids differently: the oracle must take the canonical one."""
+    rows = [line.split() for line in open(f"{GOLDEN}/fma_flip_2d.txt")
+            if line.strip() and not line.startswith("#")]
+    assert len(rows) >= 3
+    for r in rows:
+        v = [float.fromhex(t) for t in r[:6]]
+        x, c1, c2, want = np.array([v[0:2]]), v[2:4], v[4:6], int(r[6])
+
+        def canon(c):
+            dx, dy = v[0] - c[0], v[1] - c[1]
+            return dx * dx + dy * dy  # Python rounds each operation once
+
+        def fused(c):
+            dx, dy = v[0] - c[0], v[1] - c[1]
+            return _fma(dx, dx, dy * dy)
+
+        d1, d2 = canon(c1), canon(c2)
+        assert want == (0 if d1 <= d2 else 1)                      # the fixture's answer is the canonical one
+        assert (0 if fused(c1) <= fused(c2) else 1) != want        # and a contracted distance disagrees
+        a, dm = oracle.assign(x, np.array([c1, c2]))
+        assert a.tolist() == [want]
+        assert dm[0] == (d1 if want == 0 else d2)
 
 
 def test_assign_tie_goes_to_lowest_index():
