@@ -178,6 +178,24 @@ EKM_API km_status distortion_bwd(const void *x, const void *c, const int32_t *as
                          const double *grad_loss, int32_t dtype, int64_t B, int64_t n, int64_t k,
                          int32_t d, void *grad_x, void *grad_c, void *stream);
 
+/* distortion_bwd for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results (bit for bit) and errors as distortion_bwd, but the
+ * centroid-gradient sums live in a fixed scratch array that the library
+ * holds in device memory, one per GPU, until the process ends; the call
+ * allocates nothing.  The scratch holds B * k * (16 d + 4) bytes of cluster
+ * sums (rounded up to 256) plus 256: at most 8 MiB (B = 256, k = 512, d = 3
+ * takes 6.5 MiB).  Larger B * k with grad_c != NULL fails with
+ * KM_ERR_INVALID before any GPU work; grad_c == NULL needs no scratch.  The
+ * scratch is cleared on the stream at the start of every call, but all calls
+ * on one GPU share it: calls that may overlap on one GPU (different streams,
+ * or host threads without ordering) race and must be serialised by the
+ * caller.  The first call on a device looks up the scratch address on that
+ * device (hipGetSymbolAddress), with the caller's current device. */
+EKM_API km_status distortion_bwd_noalloc(const void *x, const void *c, const int32_t *assign,
+                                 const double *grad_loss, int32_t dtype, int64_t B, int64_t n,
+                                 int64_t k, int32_t d, void *grad_x, void *grad_c, void *stream);
+
 /* Human-readable reason for the last non-OK status on this thread. */
 EKM_API const char *kmeans_last_error(void);
 

@@ -26,6 +26,7 @@ from ._binding import (  # noqa: F401
     KmConfig,
     KmIterStats,
     distortion_bwd,
+    distortion_bwd_noalloc,
     distortion_fwd,
     kmeans_destroy,
     kmeans_init,

@@ -25,7 +25,8 @@ KM_FLAG_TIMING = 2
 PHASES = ("tree", "assign", "update")
 
 EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy",
-            "kmeans_phase_times", "distortion_fwd", "distortion_bwd", "kmeans_last_error")
+            "kmeans_phase_times", "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc",
+            "kmeans_last_error")
 
 
 class EKMError(RuntimeError):
@@ -70,9 +71,10 @@ def load_library(path: str = LIB_PATH):
     lib.kmeans_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
     lib.distortion_fwd.argtypes = [P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.distortion_bwd.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
+    lib.distortion_bwd_noalloc.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.kmeans_last_error.restype = ctypes.c_char_p
     for name in ("kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy", "kmeans_phase_times",
-                 "distortion_fwd", "distortion_bwd"):
+                 "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -211,6 +213,18 @@ def distortion_bwd(x: torch.Tensor, c: torch.Tensor, assign: torch.Tensor, grad_
         _pt_dtype(x), B, n, k, d, None if gx is None else gx.data_ptr(), None if gc is None else gc.data_ptr(),
         _stream()))
     return gx, gc
+
+
+def distortion_bwd_noalloc(x: torch.Tensor, c: torch.Tensor, assign: torch.Tensor, grad_loss: torch.Tensor,
+                           grad_x: torch.Tensor | None, grad_c: torch.Tensor | None):
+    """``distortion_bwd`` into caller-provided outputs, with no allocation in the library."""
+    B, n, d = x.shape
+    k = c.shape[1]
+    _check(load_library().distortion_bwd_noalloc(
+        _dev(x, "x"), _dev(c, "c"), _dev(assign, "assign", torch.int32), _dev(grad_loss, "grad_loss", torch.float64),
+        _pt_dtype(x), B, n, k, d, None if grad_x is None else _dev(grad_x, "grad_x", x.dtype),
+        None if grad_c is None else _dev(grad_c, "grad_c", c.dtype), _stream()))
+    return grad_x, grad_c
 
 
 class Distortion(torch.autograd.Function):

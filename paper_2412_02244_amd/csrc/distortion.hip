@@ -11,6 +11,8 @@
 // loss is an FP64 sum in a fixed order.  Backward: grad_x is elementwise in
 // FP64; grad_c uses exact fixed-point cluster sums (integer atomics), so
 // RN(cnt_j c_j - sum x_i) is computed once from the exact value.
+#include <mutex>
+
 #include "ekm_internal.hpp"
 
 namespace ekm {
@@ -337,6 +339,43 @@ static km_status bwd_alloc(const T *x, const T *c, const int32_t *a, const doubl
     return s;
 }
 
+// Fixed device scratch of distortion_bwd_noalloc: one copy per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host the name is only a stand-in); it uses the device
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and cached.
+static km_status noalloc_scratch(void **out)
+{
+    int dev = 0;
+    if (!hip_ok(hipGetDevice(&dev), "distortion_bwd_noalloc: hipGetDevice"))
+        return KM_ERR_HIP;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("distortion_bwd_noalloc: device index out of range");
+        return KM_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "distortion_bwd_noalloc: hipGetSymbolAddress"))
+            return KM_ERR_HIP;
+        if (!p) {
+            set_error("distortion_bwd_noalloc: hipGetSymbolAddress returned a null address");
+            return KM_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KM_OK;
+}
+
 } // namespace ekm
 
 using namespace ekm;
@@ -379,6 +418,40 @@ km_status distortion_bwd(const void *x, const void *c, const int32_t *assign, co
                                          (double *)grad_x, (double *)grad_c, st)
                   : bwd_alloc<double, 3>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
                                          (double *)grad_x, (double *)grad_c, st);
+}
+
+km_status distortion_bwd_noalloc(const void *x, const void *c, const int32_t *assign, const double *grad_loss,
+                                 int32_t dtype, int64_t B, int64_t n, int64_t k, int32_t d, void *grad_x,
+                                 void *grad_c, void *stream)
+{
+    if (!dist_args_ok(x, c, dtype, B, n, k, d))
+        return KM_ERR_INVALID;
+    if (!assign || !grad_loss) {
+        set_error("distortion_bwd_noalloc: null assignment or grad_loss");
+        return KM_ERR_INVALID;
+    }
+    if (grad_c && dist_scratch_bytes(B, k, d) > NOALLOC_SCRATCH_BYTES) {
+        set_error("distortion_bwd_noalloc: B * k * (16 d + 4) bytes of cluster sums (" +
+                  std::to_string(dist_scratch_bytes(B, k, d)) + " with alignment) exceed the fixed scratch of " +
+                  std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes");
+        return KM_ERR_INVALID;
+    }
+    void *buf = nullptr;
+    if (grad_c) {
+        km_status s = noalloc_scratch(&buf);
+        if (s != KM_OK)
+            return s;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == KM_F32)
+        return d == 2 ? bwd_t<float, 2>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
+                                        (float *)grad_x, (float *)grad_c, buf, st)
+                      : bwd_t<float, 3>((const float *)x, (const float *)c, assign, grad_loss, B, n, k,
+                                        (float *)grad_x, (float *)grad_c, buf, st);
+    return d == 2 ? bwd_t<double, 2>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
+                                     (double *)grad_x, (double *)grad_c, buf, st)
+                  : bwd_t<double, 3>((const double *)x, (const double *)c, assign, grad_loss, B, n, k,
+                                     (double *)grad_x, (double *)grad_c, buf, st);
 }
 
 } // extern "C"
