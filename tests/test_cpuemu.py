@@ -1,0 +1,110 @@
+"""The library's own kernel sources, built for the CPU (tests/cpuemu: every
+lane a fiber, wave operations and barriers as checked rendezvous, device
+memory as host memory under AddressSanitizer), run small k-means
+trajectories that are compared with the FP64 oracle.
+
+This needs no GPU.  It catches out-of-bounds accesses, wave operations or
+barriers that only part of a wave (or workgroup) reaches, and LDS hand-offs
+between lanes without a wave barrier (the emulated lanes run ahead of one
+another between rendezvous, so a missing one reads stale data).
+"""
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import ellipsoid_surfaces_3d, gaussian_mixture_2d, geo_hotspots_2d, init_centroids
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "cpuemu"))
+import build_emu  # noqa: E402
+
+KM_F64, KM_F32 = 0, 1
+KM_BRUTE, KM_INDEXED = 0, 1
+KM_FLAG_SSE = 1
+STATS = np.dtype([("n_changed", "<i8"), ("dist_evals", "<i8"), ("brute_evals", "<i8"),
+                  ("single_cand_points", "<i8"), ("rechecked", "<i8"), ("cand_total", "<i8"),
+                  ("leaves", "<i8"), ("sse", "<f8")])
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    return build_emu.build(str(tmp_path_factory.mktemp("cpuemu")))
+
+
+def _run(driver, tmp_path, mode, x, c0, iters, algo, leaf_size=0, flags=0):
+    n, d = x.shape
+    k = c0.shape[0]
+    pdt = KM_F32 if x.dtype == np.float32 else KM_F64
+    inp, out = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(inp, "wb") as f:
+        np.array([n, d, k, iters, algo, leaf_size, flags, pdt], np.int64).tofile(f)
+        np.ascontiguousarray(x).tofile(f)
+        np.ascontiguousarray(c0, np.float64).tofile(f)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    r = subprocess.run([driver, mode, str(inp), str(out)], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, f"emulated run failed ({r.returncode}):\n{r.stderr[-4000:]}"
+    raw = open(out, "rb").read()
+    if mode == "run":
+        it = int(np.frombuffer(raw[:4], np.int32)[0])
+        a = np.frombuffer(raw[4:4 + 4 * n], np.int32)
+        c = np.frombuffer(raw[4 + 4 * n:], np.float64).reshape(k, d)
+        return it, a, c
+    step = 4 * n + 8 * k * d + STATS.itemsize
+    res = []
+    for t in range(iters):
+        b = raw[t * step:(t + 1) * step]
+        a = np.frombuffer(b[:4 * n], np.int32)
+        c = np.frombuffer(b[4 * n:4 * n + 8 * k * d], np.float64).reshape(k, d)
+        st = np.frombuffer(b[4 * n + 8 * k * d:], STATS)[0]
+        res.append((a, c, st))
+    return res
+
+
+def _check(driver, tmp_path, x, c0, iters, algo, leaf_size=0):
+    ref = oracle.lloyd(x, c0, max_iter=iters)
+    got = _run(driver, tmp_path, "kmeans", x, c0, iters, algo, leaf_size, KM_FLAG_SSE)
+    for t, (a, c, st) in enumerate(got):
+        bad = np.flatnonzero(a != ref["a_hist"][t])
+        assert bad.size == 0, f"iteration {t + 1}: {bad.size} assignments differ, first at {bad[:5]}"
+        np.testing.assert_array_equal(c, ref["c_hist"][t], err_msg=f"centroids at iteration {t + 1}")
+        assert st["sse"] == pytest.approx(ref["sse"][t], rel=1e-12)
+        prev = ref["a_hist"][t - 1] if t else None
+        want = x.shape[0] if prev is None else int((ref["a_hist"][t] != prev).sum())
+        assert st["n_changed"] == want
+    return got
+
+
+@pytest.mark.parametrize("leaf_size", [0, 16])
+def test_emulated_indexed_2d(driver, tmp_path, leaf_size):
+    x = geo_hotspots_2d(3000, n_hot=12, seed=71)
+    c0 = init_centroids(x, 40, 72)
+    _check(driver, tmp_path, x, c0, 3, KM_INDEXED, leaf_size)
+
+
+def test_emulated_indexed_3d(driver, tmp_path):
+    x = ellipsoid_surfaces_3d(2500, 4, seed=73)
+    c0 = init_centroids(x, 30, 74)
+    _check(driver, tmp_path, x, c0, 3, KM_INDEXED)
+
+
+def test_emulated_brute_fp32_and_fp64(driver, tmp_path):
+    x = geo_hotspots_2d(1500, n_hot=6, seed=75)
+    c0 = init_centroids(x, 20, 76)
+    _check(driver, tmp_path, x, c0, 2, KM_BRUTE)
+    xd = gaussian_mixture_2d(1200, seed=77)
+    _check(driver, tmp_path, xd, init_centroids(xd, 15, 78), 2, KM_BRUTE)
+
+
+def test_emulated_run_until_stable(driver, tmp_path):
+    x = gaussian_mixture_2d(2000, seed=79).astype(np.float32)
+    c0 = init_centroids(x, 12, 80)
+    ref = oracle.lloyd(x, c0, max_iter=60, stop_when_stable=True)
+    it, a, c = _run(driver, tmp_path, "run", x, c0, 60, KM_INDEXED, flags=1 << 16)
+    assert it == ref["iters"]
+    np.testing.assert_array_equal(a, ref["a"])
+    np.testing.assert_array_equal(c, ref["c"])
