@@ -66,12 +66,19 @@ typedef enum {
 #define KM_FLAG_SSE 1u    /* also compute the objective sum_i D(x_i, c_in[a(i)]) each step */
 #define KM_FLAG_TIMING 2u /* record HIP events around each phase of every step (see
                              kmeans_phase_times); costs a few microseconds per step */
+#define KM_FLAG_SMALL_LISTS 4u /* testing aid: tiny candidate-list capacities, so that every
+                                  fallback path (group overflow, deferred leaves, scan of all
+                                  k centroids) runs; results are unchanged, only slower */
 
-/* Phases of one step, in order, for kmeans_phase_times. */
-#define KM_PHASE_TREE 0   /* fl32 centroids, norm bound, centroid tree */
-#define KM_PHASE_ASSIGN 1 /* candidate search, assignment, FP64 recheck, exact accumulation */
-#define KM_PHASE_UPDATE 2 /* centroid refinement and statistics */
-#define KM_NPHASE 3
+/* Phases of one step, in order, for kmeans_phase_times / kmeans_step_times. */
+#define KM_PHASE_TREE 0     /* fl32 centroids, norm bound, centroid tree, inter bounds */
+#define KM_PHASE_ASSIGN 1   /* the main assignment pass: inter-bound keeps, candidate search,
+                               assignment, FP64 recheck, exact sum updates (k_assign_waves on
+                               the indexed path, the whole brute-force assignment otherwise) */
+#define KM_PHASE_DEFERRED 2 /* the per-leaf pass for deferred leaves (indexed path; empty
+                               otherwise) */
+#define KM_PHASE_UPDATE 3   /* objective (KM_FLAG_SSE), centroid refinement and statistics */
+#define KM_NPHASE 4
 
 typedef struct km_config {
     int32_t d;           /* point dimension: 2 or 3 */
@@ -99,6 +106,17 @@ typedef struct km_iter_stats {
     int64_t cand_total;         /* sum over leaves of candidate-list lengths */
     int64_t leaves;             /* leaves of the point index (0 on the brute path) */
     double sse;                 /* sum_i D(x_i, c_in[a(i)]) if KM_FLAG_SSE, else 0 */
+    /* indexed path only (0 on the brute path): */
+    int64_t inter_leaf_points;  /* points of leaves kept whole by the inter bound (Eq. (5)):
+                                   no search, no distance, no read of the points */
+    int64_t inter_points;       /* points kept by the per-point inter bound (Eq. (4)) */
+    int64_t fallback_points;    /* points decided by scanning all k centroids (no candidate
+                                   list fitted) */
+    int64_t deferred_leaves;    /* leaves handed to the per-leaf pass (crowded candidates or a
+                                   list that did not fit the first pass) */
+    int64_t group_overflows;    /* leaf groups whose shared candidate list did not fit */
+    int64_t groups_skipped;     /* leaf groups with every leaf kept by the inter bound (no
+                                   centroid-tree descent) */
 } km_iter_stats;
 
 typedef struct km_ctx km_ctx;
@@ -146,9 +164,21 @@ EKM_API km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, 
  * (only steps of a context created with KM_FLAG_TIMING are recorded).
  *   ms:    host array of KM_NPHASE doubles, milliseconds per phase.
  *   steps: host, number of steps summed.
- * Synchronises the context's stream and clears the record.
+ * Synchronises the context's stream and clears the record (on an error
+ * nothing is cleared).
  * Errors: KM_ERR_INVALID (null argument), KM_ERR_HIP. */
 EKM_API km_status kmeans_phase_times(km_ctx *ctx, double *ms, int64_t *steps);
+
+/* GPU time per phase of each step recorded since the previous call (only
+ * steps of a context created with KM_FLAG_TIMING are recorded), oldest first.
+ *   ms:    host array of cap * KM_NPHASE doubles; ms[s * KM_NPHASE + p] receives
+ *          the milliseconds of phase p in step s, for s < min(cap, steps).
+ *   steps: host, number of steps recorded (all of them are cleared, even
+ *          beyond cap).
+ * Synchronises the context's stream.  On an error nothing is cleared.
+ * Errors: KM_ERR_INVALID (null ctx or steps, ms null with cap > 0, cap < 0),
+ * KM_ERR_HIP. */
+EKM_API km_status kmeans_step_times(km_ctx *ctx, double *ms, int64_t cap, int64_t *steps);
 
 /* Release the context and its workspace (synchronises its stream).  NULL is a no-op. */
 EKM_API km_status kmeans_destroy(km_ctx *ctx);

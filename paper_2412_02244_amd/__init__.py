@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     KM_ERR_UNSUPPORTED,
     KM_F32,
     KM_F64,
+    KM_FLAG_SMALL_LISTS,
     KM_FLAG_SSE,
     KM_FLAG_TIMING,
     KM_INDEXED,
@@ -34,6 +35,7 @@ from ._binding import (  # noqa: F401
     kmeans_phase_times,
     kmeans_run,
     kmeans_step,
+    kmeans_step_times,
     kmeans_workspace_bytes,
     load_library,
 )

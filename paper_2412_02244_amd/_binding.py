@@ -22,10 +22,11 @@ KM_F64, KM_F32 = 0, 1
 KM_BRUTE, KM_INDEXED = 0, 1
 KM_FLAG_SSE = 1
 KM_FLAG_TIMING = 2
-PHASES = ("tree", "assign", "update")
+KM_FLAG_SMALL_LISTS = 4
+PHASES = ("tree", "assign", "deferred", "update")
 
 EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy",
-            "kmeans_phase_times", "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc",
+            "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc",
             "kmeans_last_error")
 
 
@@ -44,7 +45,10 @@ class KmConfig(ctypes.Structure):
 class KmIterStats(ctypes.Structure):
     _fields_ = [("n_changed", ctypes.c_int64), ("dist_evals", ctypes.c_int64), ("brute_evals", ctypes.c_int64),
                 ("single_cand_points", ctypes.c_int64), ("rechecked", ctypes.c_int64),
-                ("cand_total", ctypes.c_int64), ("leaves", ctypes.c_int64), ("sse", ctypes.c_double)]
+                ("cand_total", ctypes.c_int64), ("leaves", ctypes.c_int64), ("sse", ctypes.c_double),
+                ("inter_leaf_points", ctypes.c_int64), ("inter_points", ctypes.c_int64),
+                ("fallback_points", ctypes.c_int64), ("deferred_leaves", ctypes.c_int64),
+                ("group_overflows", ctypes.c_int64), ("groups_skipped", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -69,11 +73,12 @@ def load_library(path: str = LIB_PATH):
     lib.kmeans_run.argtypes = [P, P, P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(KmIterStats)]
     lib.kmeans_destroy.argtypes = [P]
     lib.kmeans_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+    lib.kmeans_step_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), I64, ctypes.POINTER(I64)]
     lib.distortion_fwd.argtypes = [P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.distortion_bwd.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.distortion_bwd_noalloc.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.kmeans_last_error.restype = ctypes.c_char_p
-    for name in ("kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy", "kmeans_phase_times",
+    for name in ("kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times",
                  "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -184,6 +189,15 @@ def kmeans_phase_times(ctx: Context):
     steps = ctypes.c_int64(0)
     _check(load_library().kmeans_phase_times(ctypes.c_void_p(ctx.handle), ms, ctypes.byref(steps)))
     return {name: ms[i] for i, name in enumerate(PHASES)}, steps.value
+
+
+def kmeans_step_times(ctx: Context, cap: int = 4096):
+    """GPU milliseconds per phase of each recorded step -> list of dicts (oldest first)."""
+    ms = (ctypes.c_double * (max(1, cap) * len(PHASES)))()
+    steps = ctypes.c_int64(0)
+    _check(load_library().kmeans_step_times(ctypes.c_void_p(ctx.handle), ms, cap, ctypes.byref(steps)))
+    n = min(steps.value, cap)
+    return [{name: ms[s * len(PHASES) + i] for i, name in enumerate(PHASES)} for s in range(n)]
 
 
 def distortion_fwd(x: torch.Tensor, c: torch.Tensor):

@@ -99,8 +99,10 @@ static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
         b += (size_t)T.nnodes * 32 + (size_t)k * 16;  // node boxes, tree-ordered centroids
     }
     b += (size_t)k * (16 + 4 + d * 16 + 4); // c32, cval, acc, cnt
-    int64_t nblk = cfg->algo == KM_INDEXED ? L + heavy_waves(L) : (n + 255) / 256; // statistics rows
-    b += (size_t)nblk * (NSTAT * 8 + 8);
+    int64_t nblk = cfg->algo == KM_INDEXED ? L + HEAVY_BLOCKS : (n + 255) / 256; // statistics rows
+    b += (size_t)nblk * NSTAT * 8 + (size_t)sse_blocks(n) * 8;
+    if (cfg->algo == KM_INDEXED)
+        b += (size_t)k * (4 + 4 + 4 + 8 * d) + 4; // inter bounds, drift, previous centroids
     b += 4096;
     return b;
 }
@@ -110,6 +112,126 @@ static km_status alloc_fail(km_ctx *ctx)
     (void)ctx;
     set_error("device allocation failed");
     return KM_ERR_OOM;
+}
+
+// Host statistics from a row of NSTAT counters followed by the SSE bits.
+static void fill_stats(const km_ctx *ctx, const int64_t *h, km_iter_stats *stats)
+{
+    stats->n_changed = h[ST_CHANGED];
+    stats->dist_evals = h[ST_EVALS];
+    stats->brute_evals = ctx->n * ctx->k;
+    stats->single_cand_points = h[ST_SINGLE];
+    stats->rechecked = h[ST_RECHECK];
+    stats->cand_total = h[ST_CANDS];
+    stats->leaves = ctx->cfg.algo == KM_INDEXED ? ctx->L : 0;
+    double sse;
+    memcpy(&sse, h + NSTAT, sizeof(double));
+    stats->sse = (ctx->cfg.flags & KM_FLAG_SSE) ? sse : 0.0;
+    stats->inter_leaf_points = h[ST_KEEP_LEAF_PTS];
+    stats->inter_points = h[ST_KEEP_PTS];
+    stats->fallback_points = h[ST_FALLBACK_PTS];
+    stats->deferred_leaves = h[ST_DEFERRED];
+    stats->group_overflows = h[ST_GROUP_OVF];
+    stats->groups_skipped = h[ST_GROUP_SKIP];
+}
+
+// One step's launches: A1 tree (+ inter bounds), A2-A5 assignment passes,
+// objective, refinement.  ev: KM_NPHASE + 1 events to record at the phase
+// boundaries, or null.
+static km_status step_body(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, hipEvent_t *ev)
+{
+    auto mark = [&](int i) {
+        if (ev)
+            hipEventRecord(ev[i], ctx->stream);
+    };
+    km_status s;
+    mark(KM_PHASE_TREE);
+    if (ctx->cfg.point_dtype == KM_F32 && (s = build_centroid_tree(ctx, c_in)) != KM_OK)
+        return s;
+    mark(KM_PHASE_ASSIGN);
+    if ((s = run_assign(ctx, c_in, ev ? ev[KM_PHASE_DEFERRED] : nullptr)) != KM_OK)
+        return s;
+    mark(KM_PHASE_UPDATE);
+    const bool want_sse = (ctx->cfg.flags & KM_FLAG_SSE) != 0;
+    if (want_sse && (s = run_sse(ctx, c_in)) != KM_OK)
+        return s;
+    if ((s = run_finalize(ctx, c_in, c_out, nullptr, want_sse)) != KM_OK)
+        return s;
+    mark(KM_NPHASE);
+    if (assign_out && (s = scatter_assignment(ctx, assign_out)) != KM_OK)
+        return s;
+    return KM_OK;
+}
+
+// A step with KM_FLAG_TIMING events when the context records them: the
+// step's events join the record only when the step succeeded.
+static km_status timed_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out)
+{
+    const bool timing = (ctx->cfg.flags & KM_FLAG_TIMING) != 0;
+    if (!timing)
+        return step_body(ctx, c_in, c_out, assign_out, nullptr);
+    std::array<hipEvent_t, KM_NPHASE + 1> ev{};
+    int have = 0;
+    for (auto &e : ev) {
+        if (!ctx->ev_pool.empty()) {
+            e = ctx->ev_pool.back();
+            ctx->ev_pool.pop_back();
+        } else if (!hip_ok(hipEventCreate(&e), "hipEventCreate")) {
+            break;
+        }
+        ++have;
+    }
+    km_status s = have == KM_NPHASE + 1 ? step_body(ctx, c_in, c_out, assign_out, ev.data()) : KM_ERR_HIP;
+    if (s == KM_OK)
+        ctx->ev_steps.push_back(ev);
+    else
+        for (int i = 0; i < have; ++i)
+            ctx->ev_pool.push_back(ev[i]);
+    return s;
+}
+
+// kmeans_run's chunk of RUN_CHUNK steps on centroid array c, captured once
+// into a graph (on a private stream; launched on the context's stream).
+// Returns false when capture is not possible; the caller then launches the
+// steps one by one, with the same result.
+static bool chunk_graph(km_ctx *ctx, double *c)
+{
+    if (ctx->chunk_failed)
+        return false;
+    if (ctx->chunk_exec && ctx->chunk_c == c)
+        return true;
+    if (ctx->chunk_exec) {
+        (void)hipGraphExecDestroy(ctx->chunk_exec);
+        ctx->chunk_exec = nullptr;
+    }
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        ctx->cap_stream = nullptr;
+        ctx->chunk_failed = 1;
+        (void)hipGetLastError();
+        return false;
+    }
+    hipStream_t saved = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        for (int i = 0; ok && i < RUN_CHUNK; ++i)
+            ok = step_body(ctx, c, c, nullptr, nullptr) == KM_OK;
+        ok = hipStreamEndCapture(ctx->cap_stream, &g) == hipSuccess && ok && g;
+    }
+    ctx->stream = saved;
+    if (ok)
+        ok = hipGraphInstantiate(&ctx->chunk_exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g)
+        (void)hipGraphDestroy(g);
+    if (!ok) {
+        ctx->chunk_exec = nullptr;
+        ctx->chunk_failed = 1;
+        (void)hipGetLastError();
+        return false;
+    }
+    ctx->chunk_c = c;
+    return true;
 }
 
 } // namespace ekm
@@ -127,28 +249,66 @@ size_t kmeans_workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
 
 const char *kmeans_last_error(void) { return g_error.c_str(); }
 
+// Elapsed times of every recorded step, [step][phase]; nothing changes on error.
+static km_status recorded_times(km_ctx *ctx, std::vector<double> &out)
+{
+    if (!hip_ok(hipStreamSynchronize(ctx->stream), "phase times: hipStreamSynchronize"))
+        return KM_ERR_HIP;
+    out.assign(ctx->ev_steps.size() * KM_NPHASE, 0.0);
+    for (size_t s = 0; s < ctx->ev_steps.size(); ++s) {
+        const auto &ev = ctx->ev_steps[s];
+        for (int p = 0; p < KM_NPHASE; ++p) {
+            float t = 0.0f;
+            if (!hip_ok(hipEventElapsedTime(&t, ev[p], ev[p + 1]), "phase times: hipEventElapsedTime"))
+                return KM_ERR_HIP;
+            out[s * KM_NPHASE + p] = t;
+        }
+    }
+    return KM_OK;
+}
+
+static void release_recorded(km_ctx *ctx)
+{
+    for (auto &ev : ctx->ev_steps)
+        for (auto e : ev)
+            ctx->ev_pool.push_back(e);
+    ctx->ev_steps.clear();
+}
+
 km_status kmeans_phase_times(km_ctx *ctx, double *ms, int64_t *steps)
 {
     if (!ctx || !ms || !steps) {
         set_error("kmeans_phase_times: null argument");
         return KM_ERR_INVALID;
     }
-    if (!hip_ok(hipStreamSynchronize(ctx->stream), "kmeans_phase_times: hipStreamSynchronize"))
-        return KM_ERR_HIP;
+    std::vector<double> t;
+    km_status s = recorded_times(ctx, t);
+    if (s != KM_OK)
+        return s;
     for (int p = 0; p < KM_NPHASE; ++p)
         ms[p] = 0.0;
-    for (auto &ev : ctx->ev_steps) {
-        for (int p = 0; p < KM_NPHASE; ++p) {
-            float t = 0.0f;
-            if (!hip_ok(hipEventElapsedTime(&t, ev[p], ev[p + 1]), "kmeans_phase_times: hipEventElapsedTime"))
-                return KM_ERR_HIP;
-            ms[p] += t;
-        }
-        for (auto e : ev)
-            ctx->ev_pool.push_back(e);
-    }
+    for (size_t i = 0; i < t.size(); ++i)
+        ms[i % KM_NPHASE] += t[i];
     *steps = (int64_t)ctx->ev_steps.size();
-    ctx->ev_steps.clear();
+    release_recorded(ctx);
+    return KM_OK;
+}
+
+km_status kmeans_step_times(km_ctx *ctx, double *ms, int64_t cap, int64_t *steps)
+{
+    if (!ctx || !steps || cap < 0 || (cap > 0 && !ms)) {
+        set_error("kmeans_step_times: invalid argument");
+        return KM_ERR_INVALID;
+    }
+    std::vector<double> t;
+    km_status s = recorded_times(ctx, t);
+    if (s != KM_OK)
+        return s;
+    const int64_t n = (int64_t)ctx->ev_steps.size();
+    for (int64_t i = 0; i < (n < cap ? n : cap) * KM_NPHASE; ++i)
+        ms[i] = t[i];
+    *steps = n;
+    release_recorded(ctx);
     return KM_OK;
 }
 
@@ -166,6 +326,14 @@ km_status kmeans_destroy(km_ctx *ctx)
         hipFree(p);
     if (ctx->host_stat)
         hipHostFree(ctx->host_stat);
+    if (ctx->host_ctl)
+        hipHostFree(ctx->host_ctl);
+    if (ctx->stat_hist)
+        hipFree(ctx->stat_hist);
+    if (ctx->chunk_exec)
+        hipGraphExecDestroy(ctx->chunk_exec);
+    if (ctx->cap_stream)
+        hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return KM_OK;
 }
@@ -203,6 +371,7 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
     ctx->f = cfg->leaf_size ? cfg->leaf_size : 64;
     ctx->tile = cfg->cand_tile ? cfg->cand_tile : 1024;
     ctx->stream = (hipStream_t)stream;
+    ctx->small_lists = (cfg->flags & KM_FLAG_SMALL_LISTS) ? 1 : 0;
     hipGetDevice(&ctx->device);
 
     s = build_leaves(ctx, points);
@@ -220,7 +389,8 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
     ctx->cnt = ctx_alloc<int32_t>(ctx, k);
     ctx->nblk_stat = assign_blocks(ctx);
     ctx->stat_part = ctx_alloc<int64_t>(ctx, (size_t)ctx->nblk_stat * NSTAT);
-    ctx->sse_part = ctx_alloc<double>(ctx, ctx->nblk_stat);
+    ctx->nblk_sse = sse_blocks(n);
+    ctx->sse_part = ctx_alloc<double>(ctx, ctx->nblk_sse);
     ctx->stat_out = ctx_alloc<int64_t>(ctx, NSTAT);
     ctx->sse_out = ctx_alloc<double>(ctx, 1);
     if (!ctx->a || !ctx->c32 || !ctx->cval || !ctx->cerr || !ctx->acc || !ctx->cnt || !ctx->stat_part ||
@@ -234,19 +404,37 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
         T.cs = ctx_alloc<float4>(ctx, k);
         T.node_lo = ctx_alloc<float4>(ctx, T.nnodes);
         T.node_hi = ctx_alloc<float4>(ctx, T.nnodes);
-        ctx->leaf_prev = ctx_alloc<int32_t>(ctx, L);
+        ctx->leaf_own = ctx_alloc<int32_t>(ctx, L);
         ctx->heavy = ctx_alloc<int32_t>(ctx, L);
         ctx->heavy_cnt = ctx_alloc<int32_t>(ctx, 1);
-        if (!T.cs || !T.node_lo || !T.node_hi || !ctx->leaf_prev || !ctx->heavy || !ctx->heavy_cnt) {
+        ctx->cb_lo = ctx_alloc<float>(ctx, k);
+        ctx->cb_hi = ctx_alloc<float>(ctx, k);
+        ctx->drift = ctx_alloc<float>(ctx, k);
+        ctx->drift_max = ctx_alloc<unsigned>(ctx, 1);
+        ctx->c_prev = ctx_alloc<double>(ctx, (size_t)k * ctx->d);
+        if (!T.cs || !T.node_lo || !T.node_hi || !ctx->leaf_own || !ctx->heavy || !ctx->heavy_cnt || !ctx->cb_lo ||
+            !ctx->cb_hi || !ctx->drift || !ctx->drift_max || !ctx->c_prev) {
             kmeans_destroy(ctx);
             return alloc_fail(nullptr);
         }
-        if (!hip_ok(hipMemsetAsync(ctx->leaf_prev, 0xff, L * sizeof(int32_t), st), "hipMemsetAsync") ||
+        if (!hip_ok(hipMemsetD32Async(ctx->leaf_own, OWN_NONE, L, st), "hipMemsetD32Async") ||
             !hip_ok(hipMemsetAsync(ctx->heavy, 0, L * sizeof(int32_t), st), "hipMemsetAsync") ||
+            !hip_ok(hipMemsetAsync(ctx->drift_max, 0, sizeof(unsigned), st), "hipMemsetAsync") ||
             !hip_ok(hipMemsetAsync(ctx->heavy_cnt, 0, sizeof(int32_t), st), "hipMemsetAsync")) {
             kmeans_destroy(ctx);
             return KM_ERR_HIP;
         }
+    }
+    ctx->ctl = ctx_alloc<int32_t>(ctx, CTL_N);
+    if (!ctx->ctl || !hip_ok(hipMemsetAsync(ctx->ctl, 0, CTL_N * sizeof(int32_t), st), "hipMemsetAsync") ||
+        set_ctl(ctx, 0, 0, 1) != KM_OK) {
+        kmeans_destroy(ctx);
+        return alloc_fail(nullptr);
+    }
+    if (hipHostMalloc((void **)&ctx->host_ctl, CTL_N * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        ctx->host_ctl = nullptr;
+        kmeans_destroy(ctx);
+        return alloc_fail(nullptr);
     }
     if (hipHostMalloc((void **)&ctx->host_stat, (NSTAT + 1) * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
         ctx->host_stat = nullptr;
@@ -278,41 +466,8 @@ km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *a
         set_error("kmeans_step: null argument");
         return KM_ERR_INVALID;
     }
-    km_status s = KM_OK;
-    const bool timing = (ctx->cfg.flags & KM_FLAG_TIMING) != 0;
-    std::array<hipEvent_t, KM_NPHASE + 1> ev{};
-    if (timing) {
-        for (auto &e : ev) {
-            if (!ctx->ev_pool.empty()) {
-                e = ctx->ev_pool.back();
-                ctx->ev_pool.pop_back();
-            } else if (!hip_ok(hipEventCreate(&e), "kmeans_step: hipEventCreate")) {
-                return KM_ERR_HIP;
-            }
-        }
-        ctx->ev_steps.push_back(ev);
-    }
-    auto mark = [&](int i) {
-        if (timing)
-            hipEventRecord(ev[i], ctx->stream);
-    };
-    mark(KM_PHASE_TREE);
-    if (ctx->cfg.point_dtype == KM_F32) {
-        s = build_centroid_tree(ctx, c_in);
-        if (s != KM_OK)
-            return s;
-    }
-    mark(KM_PHASE_ASSIGN);
-    bool want_sse = (ctx->cfg.flags & KM_FLAG_SSE) != 0;
-    s = run_assign(ctx, c_in, want_sse);
+    km_status s = timed_step(ctx, c_in, c_out, assign_out);
     if (s != KM_OK)
-        return s;
-    mark(KM_PHASE_UPDATE);
-    s = run_finalize(ctx, c_in, c_out, nullptr);
-    if (s != KM_OK)
-        return s;
-    mark(KM_NPHASE);
-    if (assign_out && (s = scatter_assignment(ctx, assign_out)) != KM_OK)
         return s;
     ctx->steps_done++;
     if (stats) {
@@ -324,17 +479,7 @@ km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *a
                     "kmeans_step: stats copy") ||
             !hip_ok(hipStreamSynchronize(ctx->stream), "kmeans_step: hipStreamSynchronize"))
             return KM_ERR_HIP;
-        const int64_t *h = ctx->host_stat;
-        stats->n_changed = h[ST_CHANGED];
-        stats->dist_evals = h[ST_EVALS];
-        stats->brute_evals = ctx->n * ctx->k;
-        stats->single_cand_points = h[ST_SINGLE];
-        stats->rechecked = h[ST_RECHECK];
-        stats->cand_total = h[ST_CANDS];
-        stats->leaves = ctx->cfg.algo == KM_INDEXED ? ctx->L : 0;
-        double sse;
-        memcpy(&sse, h + NSTAT, sizeof(double));
-        stats->sse = want_sse ? sse : 0.0;
+        fill_stats(ctx, ctx->host_stat, stats);
     }
     return KM_OK;
 }
@@ -350,25 +495,74 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
         set_error("kmeans_run: max_iter must be >= 0");
         return KM_ERR_INVALID;
     }
-    int t = 0;
-    for (; t < max_iter; ++t) {
-        km_iter_stats tmp;
-        km_iter_stats *sp = per_iter ? &per_iter[t] : (stop_when_stable ? &tmp : nullptr);
-        km_status s = kmeans_step(ctx, c_inout, c_inout, nullptr, sp);
-        if (s != KM_OK)
-            return s;
-        if (stop_when_stable && t >= 1 && sp->n_changed == 0) {
-            ++t;
-            break;
+    hipStream_t st = ctx->stream;
+    if (per_iter && ctx->hist_cap < max_iter) { // per-step statistics rows on the device
+        if (!hip_ok(hipStreamSynchronize(st), "kmeans_run: hipStreamSynchronize"))
+            return KM_ERR_HIP;
+        if (ctx->stat_hist)
+            (void)hipFree(ctx->stat_hist);
+        ctx->stat_hist = nullptr;
+        ctx->hist_cap = 0;
+        if (ctx->chunk_exec) { // the captured steps write the old rows
+            (void)hipGraphExecDestroy(ctx->chunk_exec);
+            ctx->chunk_exec = nullptr;
+        }
+        if (hipMalloc((void **)&ctx->stat_hist, (size_t)max_iter * (NSTAT + 1) * sizeof(int64_t)) != hipSuccess) {
+            ctx->stat_hist = nullptr;
+            set_error("kmeans_run: device allocation failed");
+            return KM_ERR_OOM;
+        }
+        ctx->hist_cap = max_iter;
+    }
+    // The steps are launched in chunks without waiting for them; the device
+    // counts them and stops the run (every later kernel returns at once)
+    // after max_iter steps or at the first stable step.  The host looks at
+    // the device only between chunks, and only when the run may stop early.
+    km_status s = set_ctl(ctx, max_iter, stop_when_stable ? 1 : 0, 0);
+    const bool timing = (ctx->cfg.flags & KM_FLAG_TIMING) != 0;
+    for (int launched = 0; s == KM_OK && launched < max_iter;) {
+        const int chunk = max_iter - launched < RUN_CHUNK ? max_iter - launched : RUN_CHUNK;
+        if (!timing && chunk == RUN_CHUNK && chunk_graph(ctx, c_inout)) {
+            if (!hip_ok(hipGraphLaunch(ctx->chunk_exec, st), "kmeans_run: hipGraphLaunch"))
+                s = KM_ERR_HIP;
+        } else {
+            for (int i = 0; s == KM_OK && i < chunk; ++i)
+                s = timed_step(ctx, c_inout, c_inout, nullptr);
+        }
+        launched += chunk;
+        if (s == KM_OK && stop_when_stable && launched < max_iter) {
+            if (!hip_ok(hipMemcpyAsync(ctx->host_ctl, ctx->ctl, CTL_N * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                        "kmeans_run: control copy") ||
+                !hip_ok(hipStreamSynchronize(st), "kmeans_run: hipStreamSynchronize"))
+                s = KM_ERR_HIP;
+            else if (ctx->host_ctl[CTL_STOP])
+                break;
         }
     }
-    if (assign_out && ctx->steps_done > 0) {
-        km_status s = scatter_assignment(ctx, assign_out);
-        if (s != KM_OK)
-            return s;
+    if (s != KM_OK) {
+        (void)set_ctl(ctx, 0, 0, 1);
+        return s;
     }
+    if (!hip_ok(hipMemcpyAsync(ctx->host_ctl, ctx->ctl, CTL_N * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                "kmeans_run: control copy") ||
+        !hip_ok(hipStreamSynchronize(st), "kmeans_run: hipStreamSynchronize"))
+        return KM_ERR_HIP;
+    const int32_t iters = ctx->host_ctl[CTL_RUN_ITERS];
+    if ((s = set_ctl(ctx, 0, 0, 1)) != KM_OK) // back to single steps
+        return s;
+    ctx->steps_done += iters;
+    if (per_iter && iters > 0) {
+        std::vector<int64_t> rows((size_t)iters * (NSTAT + 1));
+        if (!hip_ok(hipMemcpy(rows.data(), ctx->stat_hist, rows.size() * sizeof(int64_t), hipMemcpyDeviceToHost),
+                    "kmeans_run: statistics copy"))
+            return KM_ERR_HIP;
+        for (int t = 0; t < iters; ++t)
+            fill_stats(ctx, rows.data() + (size_t)t * (NSTAT + 1), &per_iter[t]);
+    }
+    if (assign_out && ctx->steps_done > 0 && (s = scatter_assignment(ctx, assign_out)) != KM_OK)
+        return s;
     if (iters_done)
-        *iters_done = t;
+        *iters_done = iters;
     return KM_OK;
 }
 

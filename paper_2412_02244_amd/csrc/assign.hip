@@ -1,17 +1,25 @@
 // Assignment step (Algorithm 1's Assign over the point index, with its kNN
-// search over the centroid index), fused with the accumulation half of the
-// centroid update.
+// search over the centroid index), fused with the update of the exact
+// cluster sums.
 //
-// k_assign_waves: one wave per group of GROUP_LEAVES consecutive leaves;
-// see the comment at the kernel.  U, the smallest FP32 max-distance from a
-// box to a node or centroid seen so far, bounds the distance from every
-// point of the box to some centroid (the paper inherits such bounds from
-// parent nodes, Eq. (7)); nodes and centroids whose FP32 min-distance to the
-// box exceeds prune_threshold(U) are dropped.
+// k_assign_waves: one wave per group of up to GROUP_LEAVES consecutive
+// leaves; see the comment at the kernel.  Leaves that still lie within half
+// the inter bound of their cluster's centroid keep it without any search
+// (Eq. (5)); for the others, U, the smallest FP32 max-distance from a box to
+// a node or centroid seen so far, bounds the distance from every point of
+// the box to some centroid (the paper inherits such bounds from parent
+// nodes, Eq. (7)); nodes and centroids whose FP32 min-distance to the box
+// exceeds prune_threshold(U) are dropped.
+//
+// The cluster sums are exact integers (fixed point) that persist from step
+// to step: a point or leaf whose cluster changes moves its exact value from
+// the old cluster to the new one (the paper's running sum vectors, Alg. 1's
+// cluster update on a move), which gives the same integers as summing every
+// cluster afresh, in any order.
 //
 // k_assign_brute32 / k_assign_brute64: Lloyd's assignment over all k
 // centroids staged through LDS tiles (the GPU baseline; FP64 is the plain
-// canonical computation).
+// canonical computation); they sum every cluster afresh each step.
 #include "ekm_internal.hpp"
 
 namespace ekm {
@@ -35,12 +43,13 @@ struct AssignArgs {
     const double *c_in; // [k][d]
     const float4 *c32;  // [k]
     const unsigned *cmax_bits;
+    const float *cb_lo; // [k] lower bound on the distance from c_j to its nearest other centroid
     // leaves and groups
     const int32_t *leaf_start;
     int64_t L;
     const float4 *leaf_box;
     const int64_t *leaf_sum;
-    int32_t *leaf_prev;
+    int32_t *leaf_own;
     int32_t *heavy;
     int32_t *heavy_cnt;
     const int32_t *group_leaf;
@@ -48,15 +57,16 @@ struct AssignArgs {
     int64_t ngroups;
     // centroid tree
     TreeArgs T;
-    // update
+    // exact sums
     int S;
     int fix64;
     int64_t *acc;
     int32_t *cnt;
     int64_t *stat_part;
-    double *sse_part;
-    int want_sse;
     int tile;
+    // candidate capacities in use (at most the LDS capacities)
+    int sw_main, fr_main, sw_heavy, fr_heavy, heavy_m;
+    const int32_t *ctl; // device loop control: every kernel returns at once when ctl[CTL_STOP]
 };
 
 __device__ inline float err_bound(const unsigned *cmax_bits)
@@ -74,7 +84,6 @@ __device__ inline void f4_to(const float4 v, float *o)
 
 struct BlockStats {
     long long v[NSTAT];
-    double sse[G_WAVES];
 };
 
 // Per-wave LDS of the indexed kernel.  Only lanes of the owning wave touch
@@ -104,14 +113,11 @@ __device__ inline void stats_begin(BlockStats &bs)
 {
     if (threadIdx.x < NSTAT)
         bs.v[threadIdx.x] = 0;
-    if (threadIdx.x < G_WAVES)
-        bs.sse[threadIdx.x] = 0.0;
     __syncthreads();
 }
 
-// per-thread counters -> partial row `row` (fixed-order FP64 for the SSE)
-__device__ inline void stats_end(BlockStats &bs, const AssignArgs &A, const int64_t (&c)[NSTAT], double sse,
-                                 int64_t row)
+// per-thread counters -> partial row `row`
+__device__ inline void stats_end(BlockStats &bs, const AssignArgs &A, const int64_t (&c)[NSTAT], int64_t row)
 {
 #pragma unroll
     for (int q = 0; q < NSTAT; ++q) {
@@ -119,28 +125,17 @@ __device__ inline void stats_end(BlockStats &bs, const AssignArgs &A, const int6
         if (lane_id() == 0 && w)
             atomicAdd((unsigned long long *)&bs.v[q], (unsigned long long)w);
     }
-    double ws = wave_sum_f64(sse);
-    if (lane_id() == 0)
-        bs.sse[threadIdx.x / WAVE] = ws;
     __syncthreads();
     if (threadIdx.x < NSTAT)
         A.stat_part[row * NSTAT + threadIdx.x] = bs.v[threadIdx.x];
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < G_WAVES; ++w)
-            s += bs.sse[w];
-        A.sse_part[row] = s;
-    }
 }
 
 // Statistics of one workgroup of independent waves: each wave adds its
-// (wave-uniform) counters to LDS with atomics and parks its SSE in its own
-// slot; the wave that arrives last writes the workgroup's row, summing the
-// SSE slots in wave order (deterministic).  Initialised before any wave
-// diverges (the kernel's single workgroup barrier).
+// (wave-uniform) counters to LDS with atomics; the wave that arrives last
+// writes the workgroup's row.  Initialised before any wave diverges (the
+// kernel's single workgroup barrier).
 struct BlockCombine {
     unsigned long long v[NSTAT];
-    double sse[G_WAVES];
     int done;
 };
 
@@ -148,15 +143,12 @@ __device__ inline void combine_init(BlockCombine &bc)
 {
     if (threadIdx.x < NSTAT)
         bc.v[threadIdx.x] = 0;
-    if (threadIdx.x < G_WAVES)
-        bc.sse[threadIdx.x] = 0.0;
     if (threadIdx.x == 0)
         bc.done = 0;
     __syncthreads();
 }
 
-__device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const int64_t (&c)[NSTAT], double sse,
-                                   int64_t row)
+__device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const int64_t (&c)[NSTAT], int64_t row)
 {
     const int lane = lane_id();
     int64_t mine = 0;
@@ -164,11 +156,8 @@ __device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const 
     for (int q = 0; q < NSTAT; ++q)
         if (lane == q)
             mine = c[q];
-    const double ws = A.want_sse ? wave_sum_f64(sse) : 0.0;
     if (lane < NSTAT && mine)
         __hip_atomic_fetch_add(&bc.v[lane], (unsigned long long)mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (lane == 0)
-        bc.sse[threadIdx.x / WAVE] = ws;
     int last = 0;
     if (lane == 0)
         last = __hip_atomic_fetch_add(&bc.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == G_WAVES - 1;
@@ -178,12 +167,6 @@ __device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const 
     if (lane < NSTAT)
         A.stat_part[row * NSTAT + lane] =
             (int64_t)__hip_atomic_load(&bc.v[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (lane == 0) {
-        double s = 0.0;
-        for (int w = 0; w < G_WAVES; ++w)
-            s += bc.sse[w];
-        A.sse_part[row] = s;
-    }
 }
 
 // Number of lanes of the wave with `p` set (wave-uniform).
@@ -191,8 +174,9 @@ __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 
 // ------------------------------------------------------------- tree search
 // Fills sh.sc with the candidate list of box [lo, hi] and returns its
-// length, or -1 if a descent level or the list does not fit.  The whole
-// wave calls; the result is uniform.
+// length, or -1 if a descent level (more than fr / TREE_BUCKET kept nodes)
+// or the list (more than sw entries) does not fit; fr and sw are at most the
+// LDS capacities of WS.  The whole wave calls; the result is uniform.
 //
 // The descent starts at the lowest tree level with at most TREE_START_MAX
 // nodes and evaluates every node there; each later level evaluates the
@@ -202,8 +186,9 @@ __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 // holds a centroid).  Each lane keeps the min-distances of its entries in
 // its own LDS slots between the two passes of a level.
 template <int D, class WS>
-__device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A, float e, WS &sh)
+__device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A, float e, WS &sh, int sw, int fr)
 {
+    const int npar = fr / TREE_BUCKET;
     const TreeArgs &T = A.T;
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
@@ -238,12 +223,12 @@ __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A
             const bool keep = i < F && sh.fm[i] <= thr;
             const uint64_t mk = __ballot(keep);
             const int pos = cnt + __popcll(mk & lt);
-            if (keep && pos < WS::npar)
+            if (keep && pos < npar)
                 sh.par[nxt][pos] =
                     np < 0 ? i : sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
             cnt += __popcll(mk);
         }
-        if (cnt > WS::npar)
+        if (cnt > npar)
             return -1;
         wave_sync();
         np = cnt;
@@ -275,45 +260,110 @@ __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A
         const bool keep = i < F && sh.fm[i] <= thr;
         const uint64_t mk = __ballot(keep);
         const int pos = cnt + __popcll(mk & lt);
-        if (keep && pos < WS::sw) // the entry was loaded by this lane a moment ago (cache hit)
+        if (keep && pos < sw) // the entry was loaded by this lane a moment ago (cache hit)
             sh.sc[pos] = T.cs[(int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET];
         cnt += __popcll(mk);
     }
     wave_sync();
-    return cnt > WS::sw ? -1 : cnt;
+    return cnt > sw ? -1 : cnt;
 }
 
-// --------------------------------------------------------------- epilogue
-// Record the new assignment, count changes, add each point to its cluster's
-// exact fixed-point sum.
-template <int D, class TV>
-__device__ inline void finish_point(const AssignArgs &A, bool valid, int64_t p, const TV (&x)[D], int best,
-                                    int64_t &changed, double &sse)
+// --------------------------------------------------------------- exact sums
+// Fixed-point coordinates of a lane's point: (value, 0) when every value
+// fits FIX64_BITS bits, else the (hi, lo) split; zero for lanes without one.
+template <int D>
+__device__ inline void fix_point(const float (&x)[D], bool on, const AssignArgs &A, int64_t (&v0)[D],
+                                 int64_t (&v1)[D])
 {
-    if (valid) {
-        int old = A.a[p];
-        if (old != best) {
-            A.a[p] = best;
-            ++changed;
-        }
-        if (A.want_sse) {
-            double xd[D], cd[D];
-            for (int i = 0; i < D; ++i) {
-                xd[i] = (double)x[i];
-                cd[i] = A.c_in[(int64_t)best * D + i];
-            }
-            sse += sqdist64<D>(xd, cd);
-        }
-    }
-    int64_t hi[D], lo[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        if (sizeof(TV) == 4)
-            fix_split_f32((float)x[i], A.S, hi[i], lo[i]);
-        else
-            fix_split_f64((double)x[i], A.S, hi[i], lo[i]);
+        if (A.fix64) {
+            v0[i] = on ? fix_f32(x[i], A.S) : 0;
+            v1[i] = 0;
+        } else {
+            fix_split_f32(x[i], A.S, v0[i], v1[i]);
+            if (!on)
+                v0[i] = v1[i] = 0;
+        }
     }
-    wave_accumulate<D>(valid, best, hi, lo, A.acc, A.cnt);
+}
+
+// Accumulator limbs of an exact value: V = hi * 2^32 + lo with lo in [0, 2^32).
+__device__ inline void limbs(__int128 V, int64_t &hi, int64_t &lo)
+{
+    hi = (int64_t)(V >> 32);
+    lo = (int64_t)(V & (__int128)0xffffffff);
+}
+
+// Adds sign * x (exact) and sign * 1 to cluster `key` for every lane with
+// `in`.  Lanes of one cluster are summed in the wave (DPP), then lanes
+// 0..2D-1 add the limbs and lane 2D the count with integer atomics; after
+// ACC_ROUNDS clusters the remaining lanes add their own values.  Integer
+// addition makes the result independent of the order of all such updates.
+constexpr int ACC_ROUNDS = 3;
+template <int D>
+__device__ inline void wave_scatter(bool in, int key, int sign, const int64_t (&v0)[D], const int64_t (&v1)[D],
+                                    const AssignArgs &A)
+{
+    const int lane = lane_id();
+    uint64_t active = __ballot(in);
+    for (int round = 0; active; ++round) {
+        if (round == ACC_ROUNDS) {
+            if ((active >> lane) & 1ull) {
+                int64_t *ac = A.acc + (int64_t)key * D * 2;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    __int128 V = A.fix64 ? (__int128)v0[i] : (((__int128)v0[i] << 32) + (__int128)v1[i]);
+                    int64_t h, l;
+                    limbs(sign < 0 ? -V : V, h, l);
+                    atomicAdd((unsigned long long *)&ac[2 * i], (unsigned long long)h);
+                    atomicAdd((unsigned long long *)&ac[2 * i + 1], (unsigned long long)l);
+                }
+                atomicAdd(&A.cnt[key], sign);
+            }
+            break;
+        }
+        const int c = rl_i(key, __ffsll((unsigned long long)active) - 1);
+        const bool inr = in && key == c;
+        const uint64_t grp = __ballot(inr);
+        active &= ~grp;
+        int64_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            __int128 V;
+            if (A.fix64)
+                V = (__int128)wave_sum_i64(inr ? v0[i] : 0);
+            else
+                V = ((__int128)wave_sum_i64(inr ? v0[i] : 0) << 32) + (__int128)wave_sum_i64(inr ? v1[i] : 0);
+            int64_t h, l;
+            limbs(sign < 0 ? -V : V, h, l);
+            if (lane == 2 * i)
+                mine = h;
+            if (lane == 2 * i + 1)
+                mine = l;
+        }
+        if (lane < 2 * D)
+            atomicAdd((unsigned long long *)&A.acc[(int64_t)c * D * 2 + lane], (unsigned long long)mine);
+        else if (lane == 2 * D)
+            atomicAdd(&A.cnt[c], sign * __popcll(grp));
+    }
+}
+
+// Adds sign * (the leaf's precomputed exact sum) and sign * size to cluster
+// `key` (a whole leaf moving between clusters, without reading its points).
+template <int D>
+__device__ inline void leaf_sum_add(const AssignArgs &A, int64_t l, int key, int sign, int size)
+{
+    const int lane = lane_id();
+    if (lane < 2 * D) {
+        const int64_t *ls = A.leaf_sum + (l * D + (lane >> 1)) * 2;
+        __int128 V = ((__int128)ls[0] << 32) + (__int128)ls[1];
+        int64_t h, lo;
+        limbs(sign < 0 ? -V : V, h, lo);
+        atomicAdd((unsigned long long *)&A.acc[(int64_t)key * D * 2 + lane], (unsigned long long)((lane & 1) ? lo : h));
+    } else if (lane == 2 * D) {
+        atomicAdd(&A.cnt[key], sign * size);
+    }
 }
 
 template <int D>
@@ -329,93 +379,6 @@ __device__ inline int brute64_all(const double (&xd)[D], const AssignArgs &A)
         }
     }
     return bj;
-}
-
-// Exact accumulation of one leaf's points (lane = point, `valid` lanes are
-// the whole leaf) into their clusters.  The clusters present are taken one
-// at a time; a cluster's coordinate sums are wave sums of the points'
-// fixed-point values (one int64 per coordinate when every value fits
-// FIX64_BITS bits, else the hi/lo parts), its count a ballot popcount.  The
-// last cluster gets the leaf's precomputed exact sum minus what the others
-// took.  The values are then split into the (hi, lo) accumulator form and
-// lanes 0..2D-1 (sums) and 2D (count) add them with integer atomics.  A
-// leaf spread over many clusters (crowded centroids) stops reducing after
-// ACC_ROUNDS clusters; its remaining points add their own values.
-constexpr int ACC_ROUNDS = 3;
-template <int D>
-__device__ inline void accumulate_leaf(bool valid, int a, const float (&x)[D], const int64_t *lsum,
-                                       const AssignArgs &A)
-{
-    const int lane = lane_id();
-    int64_t v0[D], v1[D]; // fix64: value, 0; else hi, lo
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        if (A.fix64) {
-            v0[i] = valid ? fix_f32(x[i], A.S) : 0;
-            v1[i] = 0;
-        } else {
-            fix_split_f32(x[i], A.S, v0[i], v1[i]);
-            if (!valid)
-                v0[i] = v1[i] = 0;
-        }
-    }
-    int64_t took_hi[D], took_lo[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-        took_hi[i] = took_lo[i] = 0;
-    uint64_t active = __ballot(valid);
-    for (int round = 0; active; ++round) {
-        if (round == ACC_ROUNDS) {
-            if ((active >> lane) & 1ull) {
-                int64_t *ac = A.acc + (int64_t)a * D * 2;
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    int64_t h = v0[i], l = v1[i];
-                    if (A.fix64) {
-                        h = v0[i] >> 32;
-                        l = v0[i] - (h << 32);
-                    }
-                    atomicAdd((unsigned long long *)&ac[2 * i], (unsigned long long)h);
-                    atomicAdd((unsigned long long *)&ac[2 * i + 1], (unsigned long long)l);
-                }
-                atomicAdd(&A.cnt[a], 1);
-            }
-            break;
-        }
-        const int c = rl_i(a, __ffsll((unsigned long long)active) - 1);
-        const bool in = valid && a == c;
-        const uint64_t grp = __ballot(in);
-        active &= ~grp;
-        int64_t sh[D], sl[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            if (active == 0) {
-                sh[i] = lsum[2 * i] - took_hi[i];
-                sl[i] = lsum[2 * i + 1] - took_lo[i];
-            } else if (A.fix64) {
-                const int64_t t = wave_sum_i64(in ? v0[i] : 0);
-                sh[i] = t >> 32; // floor, so that sl is in [0, 2^32)
-                sl[i] = t - (sh[i] << 32);
-            } else {
-                sh[i] = wave_sum_i64(in ? v0[i] : 0);
-                sl[i] = wave_sum_i64(in ? v1[i] : 0);
-            }
-            took_hi[i] += sh[i];
-            took_lo[i] += sl[i];
-        }
-        int64_t mine = 0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            if (lane == 2 * i)
-                mine = sh[i];
-            if (lane == 2 * i + 1)
-                mine = sl[i];
-        }
-        if (lane < 2 * D)
-            atomicAdd((unsigned long long *)&A.acc[(int64_t)c * D * 2 + lane], (unsigned long long)mine);
-        else if (lane == 2 * D)
-            atomicAdd(&A.cnt[c], __popcll(grp));
-    }
 }
 
 // ------------------------------------------------------------- leaves
@@ -493,16 +456,11 @@ __device__ inline Best2 best2_merge(const Best2 &a, const Best2 &b)
 constexpr int SCAN_ILP = 4; // independent scans interleaved over the candidates
 
 // FP32 scan of one point (one lane) against the leaf's candidates: the list
-// entries within `thr` of the leaf box, in chunks, each candidate broadcast
-// from the lane that holds it.  Lanes whose best-vs-second margin is below
-// the error bound are decided again with canonical FP64 distances over the
-// candidates that can still be nearest: those whose FP32 lower bound does
-// not exceed the best one's upper bound (any other is strictly farther in
-// exact and in FP64 arithmetic).  Returns the centroid id.
+// entries within `thr` of the leaf box, in chunks of 64 (chunks c0,
+// c0 + cstep, ...), each candidate broadcast from the lane that holds it.
 template <int D, class WS>
-__device__ inline int assign_point(const float (&x)[D], bool valid, const float *blo, const float *bhi, float thr,
-                                   int sn, float e, const AssignArgs &A, const WS &sh,
-                                   int64_t (&st)[NSTAT])
+__device__ inline Best2 scan_list(const float (&x)[D], const float *blo, const float *bhi, float thr, int sn,
+                                  const WS &sh, int c0, int cstep)
 {
     const int lane = lane_id();
     const int nch = (sn + WAVE - 1) / WAVE;
@@ -510,7 +468,7 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
 #pragma unroll
     for (int u = 0; u < SCAN_ILP; ++u)
         bs[u] = best2_init();
-    for (int c = 0; c < nch; ++c) {
+    for (int c = c0; c < nch; c += cstep) {
         const int jl = c * WAVE + lane;
         const float4 c4 = list_entry(sh, jl, sn);
         float cl[3];
@@ -532,9 +490,26 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
 #pragma unroll
     for (int u = 1; u < SCAN_ILP; ++u)
         bs[0] = best2_merge(bs[0], bs[u]);
-    const float s1 = best2_s1(bs[0]), s2 = bs[0].s2;
-    const int id1 = best2_id(bs[0]);
-    const bool re = valid && !margin_safe(s1, s2, e);
+    return bs[0];
+}
+
+// Decision of one point from its FP32 scan result b over the leaf's
+// candidates.  Lanes with `need` whose best-vs-second margin is below the
+// error bound are decided again with canonical FP64 distances over the
+// candidates that can still be nearest: those whose FP32 lower bound does
+// not exceed the best one's upper bound (any other is strictly farther in
+// exact and in FP64 arithmetic).  Returns the centroid id (meaningful for
+// lanes with `need`).
+template <int D, class WS>
+__device__ inline int finish_point(const float (&x)[D], bool need, const Best2 &b, const float *blo,
+                                   const float *bhi, float thr, int sn, float e, const AssignArgs &A, const WS &sh,
+                                   int64_t (&st)[NSTAT])
+{
+    const int lane = lane_id();
+    const int nch = (sn + WAVE - 1) / WAVE;
+    const float s1 = best2_s1(b), s2 = b.s2;
+    const int id1 = best2_id(b);
+    const bool re = need && !margin_safe(s1, s2, e);
     const int nre = wave_count(re);
     if (nre == 0)
         return id1;
@@ -557,13 +532,13 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
                 cdl[i] = A.c_in[(int64_t)__float_as_int(c4.w) * D + i];
         uint64_t mk = __ballot(kc);
         while (mk) {
-            const int b = __ffsll((unsigned long long)mk) - 1;
+            const int bl = __ffsll((unsigned long long)mk) - 1;
             mk &= mk - 1;
-            float cc[3] = {rl_f(c4.x, b), rl_f(c4.y, b), D == 3 ? rl_f(c4.z, b) : 0.0f};
-            const int cid = rl_i(__float_as_int(c4.w), b);
+            float cc[3] = {rl_f(c4.x, bl), rl_f(c4.y, bl), D == 3 ? rl_f(c4.z, bl) : 0.0f};
+            const int cid = rl_i(__float_as_int(c4.w), bl);
             double cd[D];
             for (int i = 0; i < D; ++i)
-                cd[i] = rl_d(cdl[i], b);
+                cd[i] = rl_d(cdl[i], bl);
             if (re && sqdist32<D>(x, cc) <= s_cap) {
                 const double Dv = sqdist64<D>(xd, cd);
                 if (Dv < bd || (Dv == bd && cid < bj)) {
@@ -576,45 +551,22 @@ __device__ inline int assign_point(const float (&x)[D], bool valid, const float 
     return re ? bj : id1;
 }
 
-// Epilogue of a leaf assigned point by point: record changed assignments
-// (aold: the previous assignments, loaded by the caller), SSE terms, exact
-// cluster sums.
-template <int D>
-__device__ inline void leaf_finish(const AssignArgs &A, int64_t l, bool valid, int64_t p, const float (&x)[D],
-                                   int best, int aold, int64_t (&st)[NSTAT], double &sse)
+template <int D, class WS>
+__device__ inline int assign_point(const float (&x)[D], bool need, const float *blo, const float *bhi, float thr,
+                                   int sn, float e, const AssignArgs &A, const WS &sh, int64_t (&st)[NSTAT])
 {
-    const bool ch = valid && aold != best;
-    if (ch)
-        A.a[p] = best;
-    st[ST_CHANGED] += wave_count(ch);
-    if (A.want_sse && valid) {
-        double xd[D], cd[D];
-        for (int i = 0; i < D; ++i) {
-            xd[i] = (double)x[i];
-            cd[i] = A.c_in[(int64_t)best * D + i];
-        }
-        sse += sqdist64<D>(xd, cd);
-    }
-    accumulate_leaf<D>(valid, best, x, A.leaf_sum + l * D * 2, A);
+    const Best2 b = scan_list<D>(x, blo, bhi, thr, sn, sh, 0, 1);
+    return finish_point<D>(x, need, b, blo, bhi, thr, sn, e, A, sh, st);
 }
 
-// Fallback for a leaf whose candidate list does not fit: scan all k
-// centroids in FP32 (fl32 copies from global memory), same margin rule.
+// FP32 scan of all k centroids (fl32 copies, 64 at a time in registers, the
+// next chunk loading while this one is scanned; ascending j), same margin
+// rule, canonical FP64 brute force for the lanes that need it.  For leaves
+// whose candidate list does not fit anywhere.
 template <int D>
-__device__ void process_leaf_all(int64_t l, int s, int size, int prev, const AssignArgs &A, float e,
-                                 int64_t (&st)[NSTAT], double &sse)
+__device__ inline int scan_all(const float (&x)[D], bool need, float e, const AssignArgs &A, int64_t (&st)[NSTAT])
 {
     const int lane = lane_id();
-    const float *xs = (const float *)A.xs;
-    const bool valid = lane < size;
-    const int64_t p = (int64_t)s + lane;
-    if (lane == 0 && prev != -1)
-        A.leaf_prev[l] = -1;
-    float x[D];
-    for (int i = 0; i < D; ++i)
-        x[i] = valid ? xs[(int64_t)i * A.n + p] : 0.0f;
-    // all k centroids, 64 at a time in registers (the next chunk loading
-    // while this one is scanned), ascending j: strict < keeps the lowest index
     Best2 bs[SCAN_ILP];
 #pragma unroll
     for (int u = 0; u < SCAN_ILP; ++u)
@@ -641,127 +593,250 @@ __device__ void process_leaf_all(int64_t l, int s, int size, int prev, const Ass
         bs[0] = best2_merge(bs[0], bs[u]);
     const float s1 = best2_s1(bs[0]), s2 = bs[0].s2;
     int best = best2_id(bs[0]);
-    const bool re = valid && !margin_safe(s1, s2, e);
+    const bool re = need && !margin_safe(s1, s2, e);
+    st[ST_RECHECK] += wave_count(re);
+    st[ST_FALLBACK_PTS] += wave_count(need);
     if (re) {
         double xd[D];
         for (int i = 0; i < D; ++i)
             xd[i] = (double)x[i];
         best = brute64_all<D>(xd, A);
     }
-    const int nv = wave_count(valid);
-    st[ST_RECHECK] += wave_count(re);
-    st[ST_EVALS] += (int64_t)nv * A.k;
-    st[ST_FALLBACK_PTS] += nv;
-    leaf_finish<D>(A, l, valid, p, x, best, valid ? A.a[p] : -1, st, sse);
+    return best;
 }
+
+// A leaf as the wave sees it (uniform values).
+struct LeafJob {
+    int64_t l;
+    int s, size, own;
+    float lo[3], hi[3];
+};
 
 // Per-leaf data held by lane t of the wave for leaf l0 + t of its group.
 struct LeafRegs {
     float lo[3], hi[3];
-    int start, size, prev;
+    int start, size, own;
 };
 
 template <int D>
-__device__ inline void leaf_of(const LeafRegs &r, int t, float *blo, float *bhi)
+__device__ inline LeafJob job_of(const LeafRegs &r, int t, int64_t l0)
 {
+    LeafJob J;
+    J.l = l0 + t;
+    J.s = rl_i(r.start, t);
+    J.size = rl_i(r.size, t);
+    J.own = rl_i(r.own, t);
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        blo[i] = rl_f(r.lo[i], t);
-        bhi[i] = rl_f(r.hi[i], t);
+    for (int i = 0; i < 3; ++i) {
+        J.lo[i] = i < D ? rl_f(r.lo[i], t) : 0.0f;
+        J.hi[i] = i < D ? rl_f(r.hi[i], t) : 0.0f;
     }
+    return J;
 }
 
-// One leaf against the wave's list (the per-leaf path: no prefetch).
-template <int D, class WS>
-__device__ void process_leaf(int64_t l, int s, int size, int prev, const float *blo, const float *bhi, int sn,
-                             const AssignArgs &A, float e, const WS &sh, int64_t (&st)[NSTAT], double &sse)
+template <int D>
+__device__ inline LeafJob job_load(const AssignArgs &A, int64_t l)
+{
+    LeafJob J;
+    J.l = l;
+    J.s = A.leaf_start[l];
+    J.size = A.leaf_start[l + 1] - J.s;
+    J.own = A.leaf_own[l];
+    f4_to(A.leaf_box[2 * l], J.lo);
+    f4_to(A.leaf_box[2 * l + 1], J.hi);
+    return J;
+}
+
+// A lane's point of a leaf and its previous assignment (-1 past the leaf's
+// end or before the first step).
+template <int D>
+struct LeafPts {
+    float x[D];
+    int a;
+};
+
+template <int D>
+__device__ inline LeafPts<D> load_pts(const AssignArgs &A, const LeafJob &J)
 {
     const int lane = lane_id();
+    const bool valid = lane < J.size;
+    const int64_t p = (int64_t)J.s + lane;
     const float *xs = (const float *)A.xs;
-    float thr;
-    int j1;
-    const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
-    if (m == 0) {
-        process_leaf_all<D>(l, s, size, prev, A, e, st, sse);
+    LeafPts<D> P;
+    for (int i = 0; i < D; ++i)
+        P.x[i] = valid ? xs[(int64_t)i * A.n + p] : 0.0f;
+    P.a = valid ? A.a[p] : -1;
+    return P;
+}
+
+// A leaf with a single candidate j (Eq. (6): the whole leaf is assigned to
+// it without any distance evaluation).  A leaf that was wholly in one
+// cluster (or in none yet) moves its precomputed exact sum; a leaf of mixed
+// clusters moves the points that change (P: its points, loaded by the
+// caller when own == OWN_MIXED).
+template <int D>
+__device__ void single_leaf(const AssignArgs &A, const LeafJob &J, int j, const LeafPts<D> &P, int64_t (&st)[NSTAT])
+{
+    st[ST_SINGLE] += J.size;
+    if (J.own == j)
+        return; // already wholly in j
+    const int lane = lane_id();
+    const bool valid = lane < J.size;
+    const int64_t p = (int64_t)J.s + lane;
+    if (J.own != OWN_MIXED) {
+        if (valid)
+            A.a[p] = j;
+        st[ST_CHANGED] += J.size;
+        if (J.own >= 0)
+            leaf_sum_add<D>(A, J.l, J.own, -1, J.size);
+        leaf_sum_add<D>(A, J.l, j, +1, J.size);
+    } else {
+        const bool ch = valid && P.a != j;
+        st[ST_CHANGED] += wave_count(ch);
+        int64_t v0[D], v1[D];
+        fix_point<D>(P.x, ch, A, v0, v1);
+        wave_scatter<D>(ch && P.a >= 0, P.a, -1, v0, v1, A);
+        wave_scatter<D>(ch, j, +1, v0, v1, A);
+        if (ch)
+            A.a[p] = j;
+    }
+    if (lane == 0)
+        A.leaf_own[J.l] = j;
+}
+
+// Point-by-point decision of a leaf (lane = point, P loaded by the caller).
+// In a leaf wholly in cluster j, a point still within half the inter bound
+// of c_j keeps it (Eq. (4); c_j and cb_j are the same for the whole wave);
+// the other points are decided by `scan`.  Changed points move their exact
+// values between clusters; the leaf's common cluster is recorded for the
+// next step.
+template <int D, class ScanFn>
+__device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafPts<D> &P, float e,
+                              int64_t evals_per_point, ScanFn scan, int64_t (&st)[NSTAT])
+{
+    const int lane = lane_id();
+    const bool valid = lane < J.size;
+    const int64_t p = (int64_t)J.s + lane;
+    bool pk = false;
+    if (J.own >= 0) {
+        float cc[3];
+        f4_to(A.c32[J.own], cc);
+        pk = valid && inter_keep(A.cb_lo[J.own], sqdist32<D>(P.x, cc), e);
+        st[ST_KEEP_PTS] += wave_count(pk);
+    }
+    const bool need = valid && !pk;
+    const int nneed = wave_count(need);
+    if (nneed == 0)
+        return; // every point keeps its cluster: nothing changes
+    st[ST_EVALS] += evals_per_point * nneed;
+    int best = scan(P.x, need);
+    if (!need)
+        best = P.a;
+    const bool ch = valid && best != P.a;
+    const int nch = wave_count(ch);
+    if (nch) {
+        st[ST_CHANGED] += nch;
+        int64_t v0[D], v1[D];
+        fix_point<D>(P.x, ch, A, v0, v1);
+        wave_scatter<D>(ch && P.a >= 0, P.a, -1, v0, v1, A);
+        wave_scatter<D>(ch, best, +1, v0, v1, A);
+        if (ch)
+            A.a[p] = best;
+    }
+    const int b0 = rl_i(best, 0); // lane 0 always holds a point
+    const int own = wave_count(valid && best != b0) == 0 ? b0 : OWN_MIXED;
+    if (own != J.own && lane == 0)
+        A.leaf_own[J.l] = own;
+}
+
+// A leaf whose candidate list does not fit: every point scans all k.
+template <int D>
+__device__ void leaf_all(const AssignArgs &A, const LeafJob &J, float e, int64_t (&st)[NSTAT])
+{
+    const LeafPts<D> P = load_pts<D>(A, J);
+    decide_points<D>(A, J, P, e, A.k,
+                     [&](const float (&x)[D], bool need) { return scan_all<D>(x, need, e, A, st); }, st);
+}
+
+// Whether a leaf's decision reads its points (m: its candidate count).
+__device__ inline bool needs_points(int m, int own, int j1, int heavy_m)
+{
+    return (m >= 2 && m <= heavy_m) || (m == 1 && own == OWN_MIXED && j1 != own);
+}
+
+// A leaf against the wave's list (sn entries), after its filter; P: its
+// points when needs_points() (loaded ahead by the caller).
+template <int D, class WS>
+__device__ void leaf_listed(const AssignArgs &A, const LeafJob &J, int m, int j1, float thr, int sn, float e,
+                            const WS &sh, const LeafPts<D> &P, int64_t (&st)[NSTAT])
+{
+    if (m == 0) { // cannot happen for a well-formed tree; stay correct regardless
+        leaf_all<D>(A, J, e, st);
         return;
     }
-    const bool valid = lane < size;
-    const int64_t p = (int64_t)s + lane;
     st[ST_CANDS] += m;
-    st[ST_EVALS] += (int64_t)m * size;
-    if (lane == 0 && prev != -1)
-        A.leaf_prev[l] = -1;
-    float x[D];
-    for (int i = 0; i < D; ++i)
-        x[i] = valid ? xs[(int64_t)i * A.n + p] : 0.0f;
-    const int aold = valid ? A.a[p] : -1;
-    const int best = assign_point<D>(x, valid, blo, bhi, thr, sn, e, A, sh, st);
-    leaf_finish<D>(A, l, valid, p, x, best, aold, st, sse);
+    if (m == 1) {
+        single_leaf<D>(A, J, j1, P, st);
+        return;
+    }
+    decide_points<D>(A, J, P, e, m,
+                     [&](const float (&x)[D], bool need) {
+                         return assign_point<D>(x, need, J.lo, J.hi, thr, sn, e, A, sh, st);
+                     },
+                     st);
 }
 
-// Points and previous assignments of leaf t, as far as its filter result
-// needs them (a single-candidate leaf that keeps its cluster needs neither).
-template <int D>
-__device__ inline void load_leaf(const LeafRegs &r, int t, int m, int j1, const AssignArgs &A, float (&xv)[D],
-                                 int &av)
+// One leaf with a search of its own (no group list), in a wave with LDS
+// capacities sw / fr; returns false if the list does not fit.
+template <int D, class WS>
+__device__ bool leaf_searched(const AssignArgs &A, const LeafJob &J, float e, WS &sh, int sw, int fr,
+                              int64_t (&st)[NSTAT])
 {
-    const int lane = lane_id();
-    const float *xs = (const float *)A.xs;
-    const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
-    const int64_t p = (int64_t)s + lane;
-    const bool valid = lane < size;
-    const bool need_x = m <= HEAVY_M && (m != 1 || A.want_sse);
-    const bool need_a = m <= HEAVY_M && (m != 1 || prev != j1);
-    av = -1;
-    for (int i = 0; i < D; ++i)
-        xv[i] = 0.0f;
-    if (valid && need_x)
-        for (int i = 0; i < D; ++i)
-            xv[i] = xs[(int64_t)i * A.n + p];
-    if (valid && need_a)
-        av = A.a[p];
+    const int sn = wave_search<D>(J.lo, J.hi, A, e, sh, sw, fr);
+    if (sn < 0)
+        return false;
+    float thr;
+    int j1;
+    const int m = leaf_filter<D>(J.lo, J.hi, sn, e, sh, thr, j1);
+    const LeafPts<D> P = load_pts<D>(A, J);
+    leaf_listed<D>(A, J, m, j1, thr, sn, e, sh, P, st);
+    return true;
+}
+
+__device__ inline void defer_leaf(const AssignArgs &A, int64_t l, int64_t (&st)[NSTAT])
+{
+    st[ST_DEFERRED] += 1;
+    if (lane_id() == 0)
+        A.heavy[atomicAdd(A.heavy_cnt, 1)] = (int32_t)l;
 }
 
 // k_assign_waves: one wave per group (at most GROUP_LEAVES consecutive
 // leaves inside one compact Morton cell, see leaves.hip); the waves of a
 // workgroup are independent and the kernel has no workgroup barrier.
 //
-//  1. Group search: the centroid-tree descent for the group's bounding box
-//     gives the group list S (kNN-style pruning with the upper bound U, the
-//     node pruning of Eq. (8), made conservative for rounding).
-//  2. Leaf filter: for a leaf box b inside the group box, the same rule
-//     applied to S alone gives exactly the leaf's candidates over all k
-//     centroids: a centroid outside S has min-distance to b at least its
-//     min-distance to the group box, above prune_threshold(U_group) >=
-//     prune_threshold(U_b), and the centroid that realised U_group is in S.
-//     Lanes test S in chunks of 64; ballots give the candidate set.
-//  3. A leaf with one candidate is assigned to it without any distance
-//     evaluation (Eq. (6)'s batch assignment) and adds its precomputed exact
-//     sum to that cluster.  Otherwise each lane (one point) scans the
+//  1. Inter bound (Eq. (5)): a leaf wholly in cluster j whose box lies
+//     within half of cb_j (the distance from c_j to its nearest other
+//     centroid) of c_j stays in j; nothing about it changes.  A group whose
+//     leaves all stay skips the rest.
+//  2. Group search: the centroid-tree descent for the bounding box of the
+//     remaining leaves gives the list S (kNN-style pruning with the upper
+//     bound U, the node pruning of Eq. (8), made conservative for rounding).
+//  3. Leaf filter: for a leaf box b inside that box, the same rule applied
+//     to S alone gives exactly the leaf's candidates over all k centroids:
+//     a centroid outside S has min-distance to b at least its min-distance
+//     to the searched box, above prune_threshold(U_box) >=
+//     prune_threshold(U_b), and the centroid that realised U_box is in S.
+//  4. A leaf with one candidate is assigned to it without any distance
+//     evaluation (Eq. (6)'s batch assignment).  Otherwise each lane (one
+//     point) keeps its cluster by the inter bound (Eq. (4)) or scans the
 //     candidates in FP32; a point whose best-vs-second margin is below the
 //     error bound is decided again with canonical FP64 distances.
 //
-// If S does not fit, the wave searches leaf by leaf, and a leaf whose own
-// list does not fit scans all k centroids; results are the same.
+// If S does not fit, the wave searches leaf by leaf; a leaf whose own list
+// does not fit, or that has more than heavy_m candidates, goes to the
+// per-leaf pass.  Results are the same on every path.
 template <int D>
-__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t (&st)[NSTAT], double &sse);
-
-template <int D>
-__global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
-{
-    __shared__ WaveMain wsh[G_WAVES];
-    __shared__ BlockCombine bc;
-    combine_init(bc);
-    const int64_t g = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
-    int64_t st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double sse = 0.0;
-    if (g < A.ngroups) // whole wave; nothing in group_work synchronises across waves
-        group_work<D>(g, A, wsh[threadIdx.x / WAVE], st, sse);
-    combine_end(bc, A, st, sse, blockIdx.x);
-}
-
-template <int D>
-__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t (&st)[NSTAT], double &sse)
+__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t (&st)[NSTAT])
 {
     const int lane = lane_id();
     const float e = err_bound(A.cmax_bits);
@@ -771,171 +846,212 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t
     for (int i = 0; i < 3; ++i)
         r.lo[i] = r.hi[i] = 0.0f;
     r.start = r.size = 0;
-    r.prev = -1;
+    r.own = OWN_NONE;
     if (lane < nl) {
         const float4 bl = A.leaf_box[2 * (l0 + lane)], bh = A.leaf_box[2 * (l0 + lane) + 1];
         f4_to(bl, r.lo);
         f4_to(bh, r.hi);
         r.start = A.leaf_start[l0 + lane];
         r.size = A.leaf_start[l0 + lane + 1] - r.start;
-        r.prev = A.leaf_prev[l0 + lane];
+        r.own = A.leaf_own[l0 + lane];
     }
-    float glo[3], ghi[3];
-    f4_to(A.group_box[2 * g], glo);
-    f4_to(A.group_box[2 * g + 1], ghi);
-    const int sn = wave_search<D>(glo, ghi, A, e, sh);
+    bool keep = false;
+    if (lane < nl && r.own >= 0) {
+        float cc[3];
+        f4_to(A.c32[r.own], cc);
+        keep = inter_keep(A.cb_lo[r.own], box_maxd<D>(r.lo, r.hi, cc), e);
+    }
+    const uint64_t kept = __ballot(keep);
+    uint64_t todo = __ballot(lane < nl) & ~kept;
+    if (kept)
+        st[ST_KEEP_LEAF_PTS] += wave_sum_i32(keep ? r.size : 0);
+    if (!todo) {
+        st[ST_GROUP_SKIP] += 1;
+        return;
+    }
+    // bounding box of the leaves still to decide
+    const bool mine = (todo >> lane) & 1ull;
+    float ulo[3] = {0.0f, 0.0f, 0.0f}, uhi[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        ulo[i] = wave_min_f32(mine ? r.lo[i] : INFINITY);
+        uhi[i] = -wave_min_f32(mine ? -r.hi[i] : INFINITY);
+    }
+    const int sn = wave_search<D>(ulo, uhi, A, e, sh, A.sw_main, A.fr_main);
     if (sn < 0) {
-        // the group's list does not fit: search leaf by leaf
-        for (int t = 0; t < nl; ++t) {
-            float blo[3], bhi[3];
-            leaf_of<D>(r, t, blo, bhi);
-            const int ln = wave_search<D>(blo, bhi, A, e, sh);
-            if (ln >= 0) {
-                process_leaf<D>(l0 + t, rl_i(r.start, t), rl_i(r.size, t), rl_i(r.prev, t), blo, bhi, ln, A, e, sh,
-                                st, sse);
-            } else if (lane == 0) { // the per-leaf pass has room for it
-                A.heavy[l0 + t] = 1;
-                atomicAdd(A.heavy_cnt, 1);
-            }
+        // the list does not fit: search leaf by leaf
+        st[ST_GROUP_OVF] += 1;
+        for (uint64_t q = todo; q; q &= q - 1) {
+            const LeafJob J = job_of<D>(r, __ffsll((unsigned long long)q) - 1, l0);
+            if (!leaf_searched<D>(A, J, e, sh, A.sw_main, A.fr_main, st))
+                defer_leaf(A, J.l, st);
         }
         return;
     }
-    // filter every leaf first; lane t keeps leaf t's results
+    // filter every remaining leaf first; lane t keeps leaf t's results
     float r_thr = 0.0f;
     int r_m = 0, r_j = -1;
-    for (int t = 0; t < nl; ++t) {
+    for (uint64_t q = todo; q; q &= q - 1) {
+        const int t = __ffsll((unsigned long long)q) - 1;
         float blo[3], bhi[3];
-        leaf_of<D>(r, t, blo, bhi);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            blo[i] = i < D ? rl_f(r.lo[i], t) : 0.0f;
+            bhi[i] = i < D ? rl_f(r.hi[i], t) : 0.0f;
+        }
         float thr;
         int j1;
         const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
-        if (m != 1)
-            j1 = -1;
         if (lane == t) {
             r_thr = thr;
             r_m = m;
             r_j = j1;
         }
     }
-    float xn[D];
-    int an;
-    load_leaf<D>(r, 0, rl_i(r_m, 0), rl_i(r_j, 0), A, xn, an);
-    for (int t = 0; t < nl; ++t) {
-        float x[D];
-        for (int i = 0; i < D; ++i)
-            x[i] = xn[i];
-        const int aold = an;
-        const int m = rl_i(r_m, t), j1 = rl_i(r_j, t);
-        const float thr = rl_f(r_thr, t);
-        if (t + 1 < nl)
-            load_leaf<D>(r, t + 1, rl_i(r_m, t + 1), rl_i(r_j, t + 1), A, xn, an);
-        const int64_t l = l0 + t;
-        const int s = rl_i(r.start, t), size = rl_i(r.size, t), prev = rl_i(r.prev, t);
-        const int64_t p = (int64_t)s + lane;
-        const bool valid = lane < size;
-        if (m > HEAVY_M) { // a wave of its own in the per-leaf pass
-            if (lane == 0) {
-                A.heavy[l] = 1;
-                atomicAdd(A.heavy_cnt, 1);
-            }
+    // leaves whose decision reads their points: loaded one leaf ahead, so
+    // that the loads of the next leaf overlap the work on this one
+    uint64_t pts = __ballot(((todo >> lane) & 1ull) && needs_points(r_m, r.own, r_j, A.heavy_m));
+    LeafPts<D> Pn = {};
+    if (pts)
+        Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
+    for (uint64_t q = todo; q; q &= q - 1) {
+        const int t = __ffsll((unsigned long long)q) - 1;
+        const LeafJob J = job_of<D>(r, t, l0);
+        const int m = rl_i(r_m, t);
+        LeafPts<D> P = {};
+        if ((pts >> t) & 1ull) {
+            P = Pn;
+            pts &= pts - 1;
+            if (pts)
+                Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
+        }
+        if (m > A.heavy_m) { // a wave of its own in the per-leaf pass
+            defer_leaf(A, J.l, st);
             continue;
         }
-        st[ST_CANDS] += m;
-        if (m == 1) {
-            const int j = j1;
-            if (prev != j) {
-                const bool ch = valid && aold != j;
-                if (ch)
-                    A.a[p] = j;
-                st[ST_CHANGED] += wave_count(ch);
-                if (lane == 0)
-                    A.leaf_prev[l] = j;
-            }
-            // the leaf's exact sum and count: one atomic per lane
-            if (lane < 2 * D) {
-                int64_t *ac = A.acc + (int64_t)j * D * 2;
-                atomicAdd((unsigned long long *)&ac[lane], (unsigned long long)A.leaf_sum[l * D * 2 + lane]);
-            } else if (lane == 2 * D) {
-                atomicAdd(&A.cnt[j], size);
-            }
-            st[ST_SINGLE] += size;
-            if (A.want_sse && valid) {
-                double xd[D], cd[D];
-                for (int i = 0; i < D; ++i) {
-                    xd[i] = (double)x[i];
-                    cd[i] = A.c_in[(int64_t)j * D + i];
-                }
-                sse += sqdist64<D>(xd, cd);
-            }
-            continue;
-        }
-        if (m == 0) { // cannot happen for a well-formed tree; stay correct regardless
-            process_leaf_all<D>(l, s, size, prev, A, e, st, sse);
-            continue;
-        }
-        if (lane == 0 && prev != -1)
-            A.leaf_prev[l] = -1;
-        float blo[3], bhi[3];
-        leaf_of<D>(r, t, blo, bhi);
-        const int best = assign_point<D>(x, valid, blo, bhi, thr, sn, e, A, sh, st);
-        st[ST_EVALS] += (int64_t)m * size;
-        leaf_finish<D>(A, l, valid, p, x, best, aold, st, sse);
+        leaf_listed<D>(A, J, m, rl_i(r_j, t), rl_f(r_thr, t), sn, e, sh, P, st);
     }
 }
 
-// k_assign_heavy: the leaves k_assign_waves flagged as deferred (more than
-// HEAVY_M candidates), each with its own tree search for the leaf box, then
-// the point-by-point scan.  Such leaves sit where many centroids crowd
-// near a large sparse cell; spreading them over waves keeps one group from
-// serialising several of them.  Wave w takes leaves w, w + nw, w + 2nw, ...
-// in increasing order, so which wave sums which leaf (and the FP64 SSE
-// rounding) does not depend on timing; it clears the flags it consumed.
+template <int D>
+__global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
+{
+    if (A.ctl[CTL_STOP])
+        return; // the run is over (the whole workgroup returns)
+    __shared__ WaveMain wsh[G_WAVES];
+    __shared__ BlockCombine bc;
+    combine_init(bc);
+    const int64_t g = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
+    int64_t st[NSTAT] = {};
+    if (g < A.ngroups) // whole wave; nothing in group_work synchronises across waves
+        group_work<D>(g, A, wsh[threadIdx.x / WAVE], st);
+    combine_end(bc, A, st, blockIdx.x);
+}
+
+// k_assign_heavy: the leaves k_assign_waves deferred (a list of
+// heavy_cnt leaf ids), one workgroup per leaf: wave 0 searches the tree for
+// the leaf box (larger LDS capacities) into the workgroup's LDS, every wave
+// holds the leaf's points and scans a quarter of the candidate chunks, the
+// four partial (best, second) results meet in LDS and wave 0 finishes the
+// decision (recheck, moves of the exact sums).  A leaf whose list still
+// does not fit scans all k.  Such leaves sit where many centroids crowd near
+// a large sparse cell.  The barriers sit in a loop whose trip count is the
+// same for every wave of the workgroup.
+struct HeavyShared {
+    WaveHeavy ws;
+    uint64_t key[G_WAVES][WAVE];
+    float s2[G_WAVES][WAVE];
+    int sn;
+};
+
 template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
 {
-    __shared__ WaveHeavy wsh[G_WAVES];
+    if (A.ctl[CTL_STOP])
+        return; // the run is over (the whole workgroup returns)
+    __shared__ HeavyShared hs;
     __shared__ BlockCombine bc;
     combine_init(bc);
-    WaveHeavy &sh = wsh[threadIdx.x / WAVE];
-    const int64_t w = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
-    const int64_t nw = (int64_t)gridDim.x * G_WAVES;
+    const int w = threadIdx.x / WAVE, lane = lane_id();
     const float e = err_bound(A.cmax_bits);
-    int64_t st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double sse = 0.0;
-    if (uniform_int(*A.heavy_cnt) > 0) {
-        for (int64_t base = w; base < A.L; base += nw * WAVE) {
-            const int64_t lf = base + (int64_t)lane_id() * nw;
-            uint64_t mk = __ballot(lf < A.L && A.heavy[lf] != 0);
-            while (mk) {
-                const int b = __ffsll((unsigned long long)mk) - 1;
-                mk &= mk - 1;
-                const int64_t l = base + (int64_t)b * nw;
-                const int s = A.leaf_start[l], size = A.leaf_start[l + 1] - s, prev = A.leaf_prev[l];
-                float blo[3], bhi[3];
-                f4_to(A.leaf_box[2 * l], blo);
-                f4_to(A.leaf_box[2 * l + 1], bhi);
-                const int ln = wave_search<D>(blo, bhi, A, e, sh);
-                if (ln >= 0)
-                    process_leaf<D>(l, s, size, prev, blo, bhi, ln, A, e, sh, st, sse);
-                else
-                    process_leaf_all<D>(l, s, size, prev, A, e, st, sse);
-                if (lane_id() == 0)
-                    A.heavy[l] = 0;
+    int64_t st[NSTAT] = {};
+    const int cnt = uniform_int(*A.heavy_cnt);
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const LeafJob J = job_load<D>(A, A.heavy[i]);
+        if (w == 0) {
+            const int sn = wave_search<D>(J.lo, J.hi, A, e, hs.ws, A.sw_heavy, A.fr_heavy);
+            if (lane == 0)
+                hs.sn = sn;
+        }
+        __syncthreads();
+        const int sn = uniform_int(hs.sn);
+        float thr = 0.0f;
+        int j1 = -1, m = 0;
+        if (sn >= 0)
+            m = leaf_filter<D>(J.lo, J.hi, sn, e, hs.ws, thr, j1); // every wave: the same m
+        if (m >= 2) {
+            const LeafPts<D> P = load_pts<D>(A, J);
+            const Best2 b = scan_list<D>(P.x, J.lo, J.hi, thr, sn, hs.ws, w, G_WAVES);
+            hs.key[w][lane] = b.key;
+            hs.s2[w][lane] = b.s2;
+            __syncthreads();
+            if (w == 0) {
+                Best2 t = b;
+                for (int u = 1; u < G_WAVES; ++u)
+                    t = best2_merge(t, Best2{hs.key[u][lane], hs.s2[u][lane]});
+                st[ST_CANDS] += m;
+                decide_points<D>(A, J, P, e, m,
+                                 [&](const float (&x)[D], bool need) {
+                                     return finish_point<D>(x, need, t, J.lo, J.hi, thr, sn, e, A, hs.ws, st);
+                                 },
+                                 st);
+            }
+        } else if (w == 0) {
+            if (sn < 0) {
+                leaf_all<D>(A, J, e, st);
+            } else {
+                const LeafPts<D> P = load_pts<D>(A, J);
+                leaf_listed<D>(A, J, m, j1, thr, sn, e, hs.ws, P, st);
             }
         }
+        __syncthreads(); // the workgroup's LDS is free for the next leaf
     }
-    combine_end(bc, A, st, sse, (A.ngroups + G_WAVES - 1) / G_WAVES + blockIdx.x);
+    combine_end(bc, A, st, (A.ngroups + G_WAVES - 1) / G_WAVES + blockIdx.x);
 }
 
 // ------------------------------------------------------------- brute force
+// Record the new assignment, count changes, add the point to its cluster's
+// exact fixed-point sum (the brute path sums every cluster afresh).
+template <int D, class TV>
+__device__ inline void finish_point(const AssignArgs &A, bool valid, int64_t p, const TV (&x)[D], int best,
+                                    int64_t &changed)
+{
+    if (valid) {
+        int old = A.a[p];
+        if (old != best) {
+            A.a[p] = best;
+            ++changed;
+        }
+    }
+    int64_t hi[D], lo[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (sizeof(TV) == 4)
+            fix_split_f32((float)x[i], A.S, hi[i], lo[i]);
+        else
+            fix_split_f64((double)x[i], A.S, hi[i], lo[i]);
+    }
+    wave_accumulate<D>(valid, best, hi, lo, A.acc, A.cnt);
+}
 template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_brute32(AssignArgs A)
 {
+    if (A.ctl[CTL_STOP])
+        return; // the run is over (the whole workgroup returns)
     __shared__ BlockStats bs;
     extern __shared__ float4 tile[];
     stats_begin(bs);
-    int64_t st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double sse = 0.0;
+    int64_t st[NSTAT] = {};
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = p < A.n;
     const float *xs = (const float *)A.xs;
@@ -975,19 +1091,20 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_brute32(AssignArgs A)
     st[ST_RECHECK] += re ? 1 : 0;
     st[ST_EVALS] += valid ? A.k : 0;
     int64_t ch = 0;
-    finish_point<D, float>(A, valid, p, x, best, ch, sse);
+    finish_point<D, float>(A, valid, p, x, best, ch);
     st[ST_CHANGED] += ch;
-    stats_end(bs, A, st, sse, blockIdx.x);
+    stats_end(bs, A, st, blockIdx.x);
 }
 
 template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_brute64(AssignArgs A)
 {
+    if (A.ctl[CTL_STOP])
+        return; // the run is over (the whole workgroup returns)
     __shared__ BlockStats bs;
     extern __shared__ double dtile[];
     stats_begin(bs);
-    int64_t st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double sse = 0.0;
+    int64_t st[NSTAT] = {};
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = p < A.n;
     const double *xs = (const double *)A.xs;
@@ -1012,13 +1129,77 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_brute64(AssignArgs A)
     }
     st[ST_EVALS] += valid ? A.k : 0;
     int64_t ch = 0;
-    finish_point<D, double>(A, valid, p, x, bj, ch, sse);
+    finish_point<D, double>(A, valid, p, x, bj, ch);
     st[ST_CHANGED] += ch;
-    stats_end(bs, A, st, sse, blockIdx.x);
+    stats_end(bs, A, st, blockIdx.x);
+}
+
+// ------------------------------------------------------------- objective
+// SSE of the step (Eq. (1)'s objective against the centroids assigned to):
+// block b sums the canonical D64 of points [b * SSE_CHUNK, (b + 1) *
+// SSE_CHUNK) in a fixed order, so the value does not depend on scheduling.
+constexpr int SSE_THREADS = 256;
+constexpr int SSE_CHUNK = SSE_THREADS * 16;
+
+int64_t sse_blocks(int64_t n) { return (n + SSE_CHUNK - 1) / SSE_CHUNK; }
+
+template <class T, int D>
+__global__ void __launch_bounds__(SSE_THREADS) k_sse(const T *xs, const int32_t *a, const double *c, int64_t n,
+                                                     double *part, const int32_t *ctl)
+{
+    if (ctl[CTL_STOP])
+        return;
+    __shared__ double red[SSE_THREADS];
+    const int64_t p0 = (int64_t)blockIdx.x * SSE_CHUNK;
+    double s = 0.0;
+    for (int q = 0; q < SSE_CHUNK / SSE_THREADS; ++q) {
+        const int64_t p = p0 + (int64_t)q * SSE_THREADS + threadIdx.x;
+        if (p < n) {
+            double xd[D], cd[D];
+            const int j = a[p];
+            for (int i = 0; i < D; ++i) {
+                xd[i] = (double)xs[(int64_t)i * n + p];
+                cd[i] = c[(int64_t)j * D + i];
+            }
+            s += sqdist64<D>(xd, cd);
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = SSE_THREADS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = red[0];
+}
+
+km_status run_sse(km_ctx *ctx, const double *c_in)
+{
+    const unsigned nb = (unsigned)sse_blocks(ctx->n);
+    hipStream_t st = ctx->stream;
+    const bool f32 = ctx->cfg.point_dtype == KM_F32;
+    if (ctx->d == 2) {
+        if (f32)
+            hipLaunchKernelGGL((k_sse<float, 2>), dim3(nb), dim3(SSE_THREADS), 0, st, (const float *)ctx->xs, ctx->a,
+                               c_in, ctx->n, ctx->sse_part, ctx->ctl);
+        else
+            hipLaunchKernelGGL((k_sse<double, 2>), dim3(nb), dim3(SSE_THREADS), 0, st, (const double *)ctx->xs,
+                               ctx->a, c_in, ctx->n, ctx->sse_part, ctx->ctl);
+    } else {
+        if (f32)
+            hipLaunchKernelGGL((k_sse<float, 3>), dim3(nb), dim3(SSE_THREADS), 0, st, (const float *)ctx->xs, ctx->a,
+                               c_in, ctx->n, ctx->sse_part, ctx->ctl);
+        else
+            hipLaunchKernelGGL((k_sse<double, 3>), dim3(nb), dim3(SSE_THREADS), 0, st, (const double *)ctx->xs,
+                               ctx->a, c_in, ctx->n, ctx->sse_part, ctx->ctl);
+    }
+    return hip_ok(hipGetLastError(), "objective launch") ? KM_OK : KM_ERR_HIP;
 }
 
 // ------------------------------------------------------------- driver
-static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
+static AssignArgs make_args(km_ctx *ctx, const double *c_in)
 {
     AssignArgs A;
     A.xs = ctx->xs;
@@ -1028,11 +1209,12 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
     A.c_in = c_in;
     A.c32 = ctx->c32;
     A.cmax_bits = (const unsigned *)ctx->cerr;
+    A.cb_lo = ctx->cb_lo;
     A.leaf_start = ctx->leaf_start;
     A.L = ctx->L;
     A.leaf_box = (const float4 *)ctx->leaf_box;
     A.leaf_sum = ctx->leaf_sum;
-    A.leaf_prev = ctx->leaf_prev;
+    A.leaf_own = ctx->leaf_own;
     A.heavy = ctx->heavy;
     A.heavy_cnt = ctx->heavy_cnt;
     A.group_leaf = ctx->group_leaf;
@@ -1044,9 +1226,21 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
     A.acc = ctx->acc;
     A.cnt = ctx->cnt;
     A.stat_part = ctx->stat_part;
-    A.sse_part = ctx->sse_part;
-    A.want_sse = want_sse ? 1 : 0;
     A.tile = ctx->tile;
+    A.ctl = ctx->ctl;
+    if (ctx->small_lists) { // tiny capacities: every fallback path runs (tests)
+        A.sw_main = 16;
+        A.fr_main = 64;
+        A.sw_heavy = 32;
+        A.fr_heavy = 128;
+        A.heavy_m = 2;
+    } else {
+        A.sw_main = SW_MAIN;
+        A.fr_main = FR_MAIN;
+        A.sw_heavy = SW_HEAVY;
+        A.fr_heavy = FR_HEAVY;
+        A.heavy_m = HEAVY_M;
+    }
     return A;
 }
 
@@ -1054,26 +1248,31 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in, bool want_sse)
 int64_t assign_blocks(const km_ctx *ctx)
 {
     if (ctx->cfg.algo == KM_INDEXED)
-        return (ctx->ngroups + G_WAVES - 1) / G_WAVES + heavy_waves(ctx->L) / G_WAVES;
+        return (ctx->ngroups + G_WAVES - 1) / G_WAVES + HEAVY_BLOCKS;
     return (ctx->n + ASSIGN_THREADS - 1) / ASSIGN_THREADS;
 }
 
-km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse)
+// Launches the assignment passes; `between` (may be null) is recorded between
+// the main pass and the per-leaf pass.
+km_status run_assign(km_ctx *ctx, const double *c_in, hipEvent_t between)
 {
     hipStream_t st = ctx->stream;
-    AssignArgs A = make_args(ctx, c_in, want_sse);
+    AssignArgs A = make_args(ctx, c_in);
     unsigned nb = (unsigned)assign_blocks(ctx);
     const unsigned nwg = (unsigned)((ctx->ngroups + G_WAVES - 1) / G_WAVES);
     const int D = ctx->d;
     if (ctx->cfg.algo == KM_INDEXED) {
-        const unsigned nhw = (unsigned)(heavy_waves(ctx->L) / G_WAVES);
-        if (D == 2) {
+        const unsigned nhw = (unsigned)HEAVY_BLOCKS;
+        if (D == 2)
             hipLaunchKernelGGL(k_assign_waves<2>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
-            hipLaunchKernelGGL(k_assign_heavy<2>, dim3(nhw), dim3(ASSIGN_THREADS), 0, st, A);
-        } else {
+        else
             hipLaunchKernelGGL(k_assign_waves<3>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
+        if (between)
+            hipEventRecord(between, st);
+        if (D == 2)
+            hipLaunchKernelGGL(k_assign_heavy<2>, dim3(nhw), dim3(ASSIGN_THREADS), 0, st, A);
+        else
             hipLaunchKernelGGL(k_assign_heavy<3>, dim3(nhw), dim3(ASSIGN_THREADS), 0, st, A);
-        }
     } else if (ctx->cfg.point_dtype == KM_F32) {
         size_t lds = (size_t)ctx->tile * sizeof(float4);
         if (D == 2)
@@ -1087,6 +1286,8 @@ km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse)
         else
             hipLaunchKernelGGL(k_assign_brute64<3>, dim3(nb), dim3(ASSIGN_THREADS), lds, st, A);
     }
+    if (ctx->cfg.algo != KM_INDEXED && between)
+        hipEventRecord(between, st);
     if (!hip_ok(hipGetLastError(), "assign launch"))
         return KM_ERR_HIP;
     return KM_OK;

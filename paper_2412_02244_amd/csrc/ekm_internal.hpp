@@ -19,32 +19,50 @@ constexpr int WAVE = 64;
 constexpr int MAX_LEAF = 64;     // a leaf fits one wave
 constexpr int GROUP_LEAVES = 8;  // consecutive leaves sharing one centroid-tree descent (one wave)
 constexpr int HEAVY_M = 24;      // leaves with more candidates get a wave of their own
-// Waves of the per-leaf pass: L/16, at least 1024, at most 65536 (a multiple
-// of 4: four waves share one statistics row).
-inline int64_t heavy_waves(int64_t L)
-{
-    int64_t w = L / 16;
-    w = w < 1024 ? 1024 : (w > 65536 ? 65536 : w);
-    return (w + 3) / 4 * 4;
-}
+// Workgroups of the per-leaf pass (one per CU): workgroup b takes the
+// deferred leaves b, b + HEAVY_BLOCKS, ... of the step's list.
+constexpr int HEAVY_BLOCKS = 256;
 // Group cells: the largest Morton cells with at most this many points (a
 // multiple of the leaf size, so cells are unions of whole leaves).
 inline constexpr int group_cell_points(int f) { return 8 * f; }
 constexpr int TREE_BUCKET = 8;   // centroids per centroid-tree leaf bucket
 constexpr int TREE_MAX_LEVELS = 8;
 constexpr int TREE_START_MAX = 512; // nodes a descent evaluates at its first level
-constexpr int NSTAT = 8;       // per-block statistics slots (see StatSlot)
+constexpr int NSTAT = 12;      // per-block statistics slots (see StatSlot); even (read as pairs)
 constexpr int MAX_FIX_BITS = 94;
 constexpr int FIX64_BITS = 56;  // per-point fixed-point values of this size sum over a wave within int64
 
 enum StatSlot {
     ST_CHANGED = 0,
     ST_EVALS = 1,
-    ST_SINGLE = 2,
+    ST_SINGLE = 2,        // points in leaves with a single candidate (batch-assigned)
     ST_RECHECK = 3,
     ST_CANDS = 4,
-    ST_FALLBACK_PTS = 5, // points decided by a fallback search (group candidate set too large)
+    ST_FALLBACK_PTS = 5,  // points decided by the scan of all k centroids (no candidate list fitted)
+    ST_KEEP_LEAF_PTS = 6, // points of leaves kept whole by the inter bound (Eq. (5))
+    ST_KEEP_PTS = 7,      // points kept by the per-point inter bound (Eq. (4))
+    ST_DEFERRED = 8,      // leaves handed to the per-leaf pass
+    ST_GROUP_OVF = 9,     // groups whose candidate list did not fit (searched leaf by leaf)
+    ST_GROUP_SKIP = 10,   // groups with every leaf kept: no centroid-tree descent
 };
+
+// Device-side loop control of a context (ctl[]): the step kernels of a
+// kmeans_run return at once when CTL_STOP is set, so a run can be launched
+// in chunks of steps (as graphs) without the host waiting for each step.
+enum CtlSlot {
+    CTL_STOP = 0,      // nonzero: the run is over (stable, or max_iter steps done)
+    CTL_RUN_ITERS = 1, // steps done by the current run
+    CTL_STEPS = 2,     // steps done by the context (0: no previous centroids)
+    CTL_MAX_ITER = 3,  // the current run's max_iter (a large value outside runs)
+    CTL_STABLE = 4,    // the current run stops when the assignment is stable
+    CTL_N = 8,
+};
+constexpr int RUN_CHUNK = 8; // steps per launch group (graph) of kmeans_run
+
+// Common cluster of a leaf's points (leaf_own): a centroid id when every
+// point of the leaf is assigned to it, else one of these.
+constexpr int OWN_MIXED = -1; // points of several clusters
+constexpr int OWN_NONE = -2;  // not assigned yet (before the first step)
 
 // ------------------------------------------------------------------------
 // Morton codes on a 2^b grid per dimension over the data bounding box.
@@ -135,6 +153,18 @@ __device__ inline float prune_threshold(float U, float e)
 {
     float r = (sqrtf(U + TAU) * MARGIN_UP + 2.0f * e) * MARGIN_UP * MARGIN_UP;
     return r * r * MARGIN_UP + TAU;
+}
+
+// Inter bound (Eq. (4), (5)): every point within exact distance r of c_j,
+// where every other centroid is at exact distance >= cb from c_j, is
+// strictly nearer to c_j when 2 r < cb (triangle inequality).  s: an FP32
+// squared distance (or box max-distance) bounding r through dist_hi;
+// cb_lo: a lower bound on cb.  The factor 1 + 2^-14 keeps the gap far above
+// the FP32 rounding of the test and the FP64 rounding of the canonical
+// distances, so the kept centroid is also the strict FP64 argmin.
+__device__ inline bool inter_keep(float cb_lo, float s, float e)
+{
+    return cb_lo > 2.0f * dist_hi(s, e) * (1.0f + 0x1p-14f);
 }
 
 template <int D>
@@ -504,8 +534,8 @@ struct km_ctx {
     int32_t *leaf_start = nullptr;// [L+1]
     float *leaf_box = nullptr;    // [L][2][4] lo xyz pad, hi xyz pad
     int64_t *leaf_sum = nullptr;  // [L][d][2] exact fixed-point sums
-    int32_t *leaf_prev = nullptr; // [L] whole-leaf cluster of the previous step, or -1
-    int32_t *heavy = nullptr;     // [L] 1 for leaves deferred to the per-leaf pass of this step
+    int32_t *leaf_own = nullptr;  // [L] cluster of every point of the leaf, OWN_MIXED or OWN_NONE
+    int32_t *heavy = nullptr;     // [L] ids of the leaves deferred to the per-leaf pass of this step
     int32_t *heavy_cnt = nullptr; // [1] their number (reset by the finalize kernel)
     // A1: centroid tree
     float4 *c32 = nullptr;        // [k] fl32(c) in caller order
@@ -513,6 +543,11 @@ struct km_ctx {
     int32_t *cval = nullptr, *cval2 = nullptr;
     ekm::TreeArgs tree{};
     float *cerr = nullptr;        // [1] bits of an FP32 upper bound on max_j ||c_j||
+    // inter bound (Eq. (3)): cb_lo[j] <= min_{i != j} ||c_i - c_j|| <= cb_hi[j] (exact distances)
+    float *cb_lo = nullptr, *cb_hi = nullptr; // [k]
+    double *c_prev = nullptr;     // [k][d] centroids of the previous step (drift, Eq. (9))
+    unsigned *drift_max = nullptr; // [1] bits of max_j drift (large-k path)
+    float *drift = nullptr;       // [k] drift of each centroid (large-k path)
     // groups: runs of at most GROUP_LEAVES consecutive leaves inside one group cell
     int64_t ngroups = 0;
     int32_t *group_leaf = nullptr; // [ngroups+1] first leaf of each group
@@ -522,7 +557,8 @@ struct km_ctx {
     int32_t *cnt = nullptr;       // [k]
     int64_t nblk_stat = 0;
     int64_t *stat_part = nullptr; // [nblk][NSTAT]
-    double *sse_part = nullptr;   // [nblk]
+    int64_t nblk_sse = 0;
+    double *sse_part = nullptr;   // [nblk_sse] objective partials of the SSE pass
     int64_t *stat_out = nullptr;  // [NSTAT]
     double *sse_out = nullptr;    // [1]
     int64_t *host_stat = nullptr; // pinned [NSTAT + 1]
@@ -532,6 +568,16 @@ struct km_ctx {
     uint32_t *scan_tmp = nullptr;
     ekm::Scratch mem;
     int steps_done = 0;
+    int32_t *ctl = nullptr;       // [CTL_N] device-side loop control
+    int32_t *host_ctl = nullptr;  // pinned [CTL_N]
+    int64_t *stat_hist = nullptr; // [hist_cap][NSTAT + 1] per-step statistics of a run
+    int64_t hist_cap = 0;
+    // kmeans_run's captured chunk of RUN_CHUNK steps (one per centroid array)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t chunk_exec = nullptr;
+    const double *chunk_c = nullptr;
+    int chunk_failed = 0;
+    int small_lists = 0;          // KM_FLAG_SMALL_LISTS: tiny candidate capacities (tests of the fallbacks)
     // KM_FLAG_TIMING: five events per recorded step (phase boundaries)
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::array<hipEvent_t, KM_NPHASE + 1>> ev_steps;
@@ -572,10 +618,13 @@ hipError_t tree_setup();
 void tree_layout(int64_t k, TreeArgs &T);
 
 // assign.hip
-km_status run_assign(km_ctx *ctx, const double *c_in, bool want_sse);
+km_status run_assign(km_ctx *ctx, const double *c_in, hipEvent_t between);
+km_status run_sse(km_ctx *ctx, const double *c_in);
+int64_t sse_blocks(int64_t n);
 
 // reduce.hip
-km_status run_finalize(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out);
+km_status run_finalize(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, bool with_sse);
+km_status set_ctl(km_ctx *ctx, int32_t max_iter, int32_t stable, int32_t reset_run);
 km_status scatter_assignment(km_ctx *ctx, int32_t *assign_out);
 
 } // namespace ekm

@@ -20,6 +20,13 @@ constexpr int SMALL_K = 4096;
 constexpr int TREE_THREADS = 1024;
 constexpr int TREE_WAVES = TREE_THREADS / WAVE;
 
+__device__ inline void f4_to3(const float4 v, float *o)
+{
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+}
+
 __device__ inline void box_empty(float4 &lo, float4 &hi)
 {
     lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
@@ -65,14 +72,110 @@ __device__ inline float centroid_prep_one(const double *c, int64_t j, const Grid
     return nb;
 }
 
+// Upper bound (FP32) on the drift ||c_j - c_prev_j|| of a centroid since the
+// previous step (Algorithm 1 computes it with the refined centroids).
+template <int D>
+__device__ inline float drift_bound(const double *c, const double *cp)
+{
+    double s = 0.0;
+    for (int i = 0; i < D; ++i) {
+        const double t = c[i] - cp[i];
+        s += t * t;
+    }
+    const double r = sqrt(s) * (1.0 + 0x1p-40);
+    float f = (float)r;
+    if ((double)f < r)
+        f = nextafterf(f, INFINITY);
+    return f;
+}
+
+// Inter bound of Eq. (3): the distance from a centroid to its nearest other
+// centroid, found by a nearest-neighbour search of the centroid tree (the
+// paper runs a 2-NN query per centroid, whose first hit is the centroid
+// itself).  Returns the smallest FP32 squared distance from cj (tree
+// position self) to any other centroid, or s0 if none is below s0.  A node
+// whose box min-distance is not below the best so far is skipped (its
+// members' FP32 distances are at least that min-distance).  The bucket of
+// `self` is scanned first, for a good starting bound.  The walk is
+// depth-first over the implicit 8-ary tree without a stack: after a node
+// it moves to the next sibling, or up to the parent's next sibling, so all
+// its state stays in registers.
+//   cent(q): fl32 centroid at tree position q;  box(l, i, lo, hi): box of
+//   node i of level l.
+//   lev_size: node count of every level (a copy in LDS: the level is
+//   thread-dependent, and indexing the kernel-argument copy with it would
+//   move that copy to scratch memory); nlev: levels.
+template <int D, class Cent, class Box>
+__device__ float nn_search(int64_t self, const float *cj, float s0, const int64_t *lev_size, int nlev, int64_t k,
+                           Cent cent, Box box)
+{
+    float best = s0;
+    const int64_t b0 = self / TREE_BUCKET;
+    for (int64_t q = b0 * TREE_BUCKET; q < k && q < (b0 + 1) * TREE_BUCKET; ++q)
+        if (q != self) {
+            float c[3];
+            cent(q, c);
+            best = fminf(best, sqdist32<D>(cj, c));
+        }
+    const int top = nlev - 1;
+    if (top == 0)
+        return best; // a single bucket: scanned above
+    int lev = top - 1;
+    int64_t idx = 0; // first child of the root
+    while (true) {
+        float lo[3], hi[3];
+        box(lev, idx, lo, hi);
+        const bool enter = box_mind<D>(lo, hi, cj) < best;
+        if (enter && lev > 0) { // descend to the first child
+            --lev;
+            idx *= 8;
+            continue;
+        }
+        if (enter && idx != b0) // a bucket: scan its centroids
+            for (int64_t q = idx * TREE_BUCKET; q < k && q < (idx + 1) * TREE_BUCKET; ++q) {
+                float c[3];
+                cent(q, c);
+                best = fminf(best, sqdist32<D>(cj, c));
+            }
+        // next sibling, or climb until a parent has one
+        while (lev < top && ((idx & 7) == 7 || idx + 1 >= lev_size[lev])) {
+            idx >>= 3;
+            ++lev;
+        }
+        if (lev >= top)
+            break;
+        ++idx;
+    }
+    return best;
+}
+
+// FP32 squared-distance bound for the search of centroid j: with U an upper
+// bound on the exact distance from c_j to its nearest other centroid, the
+// FP32 distance between their fl32 copies is at most lo_inverse(U, 2e).
+// Eq. (9): U = cb_j of the previous step + drift of c_j + the largest drift.
+__device__ inline float nn_bound(bool have_prev, float cb_hi_prev, float drift_j, float drift_max, float e)
+{
+    if (!have_prev)
+        return INFINITY;
+    const float U = (cb_hi_prev + drift_j + drift_max) * MARGIN_UP * MARGIN_UP;
+    return lo_inverse(U, 2.0f * e);
+}
+
+__device__ inline float err_of(float cmax) { return cmax * 0x1p-24f * (1.0f + 0x1p-20f) + 0x1p-100f; }
+
 // ------------------------------------------------------------------ small k
 // Everything in one workgroup, LDS-resident after one read of the centroids:
 // prep, stable LSD radix sort (8-bit digits) of the top 16 key bits, the
 // tree-ordered copy and every node box; global memory is only written.
 template <int D>
 __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, int64_t k, Grid g, TreeArgs T,
-                                                             float4 *c32, unsigned *cmax_bits)
+                                                             float4 *c32, unsigned *cmax_bits, double *c_prev,
+                                                             float *cb_lo, float *cb_hi, const int32_t *ctl)
 {
+    if (ctl[CTL_STOP])
+        return; // the run is over (the whole workgroup returns)
+    const int have_prev = ctl[CTL_STEPS] > 0;
+    __shared__ float cmax_sh, dmax_sh;
     extern __shared__ unsigned char smem[];
     float4 *cq = (float4 *)smem;              // [SMALL_K] fl32 centroids, caller order
     uint32_t *key = (uint32_t *)(cq + SMALL_K); // [SMALL_K]
@@ -104,6 +207,7 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, in
         for (int w = 0; w < TREE_WAVES; ++w)
             m = fmaxf(m, red[w]);
         *cmax_bits = __float_as_uint(m);
+        cmax_sh = m;
     }
     // two stable passes over 8-bit digits
     for (int pass = 0; pass < 2; ++pass) {
@@ -210,27 +314,143 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, in
         }
         __syncthreads();
     }
+    // inter bound: drift since the previous step, then the nearest-neighbour
+    // search of every centroid over the LDS tree
+    __shared__ int64_t lev_size_sh[TREE_MAX_LEVELS], lev_off_sh[TREE_MAX_LEVELS];
+    if (tid < TREE_MAX_LEVELS) {
+        lev_size_sh[tid] = T.lev_size[tid];
+        lev_off_sh[tid] = T.lev_off[tid];
+    }
+    float dm = 0.0f;
+    if (have_prev)
+        for (int t = tid; t < kk; t += TREE_THREADS) {
+            const int j = (int)id[t];
+            dm = fmaxf(dm, drift_bound<D>(c + (int64_t)j * D, c_prev + (int64_t)j * D));
+        }
+    dm = -wave_min_f32(-dm);
+    if (lane == 0)
+        red[wid] = dm;
+    __syncthreads();
+    if (tid == 0) {
+        float m = 0.0f;
+        for (int w = 0; w < TREE_WAVES; ++w)
+            m = fmaxf(m, red[w]);
+        dmax_sh = m;
+    }
+    __syncthreads();
+    const float e = err_of(cmax_sh), dmax = dmax_sh;
+    auto cent = [&](int64_t q, float *o) {
+        const float4 p = cq[id[q]];
+        o[0] = p.x;
+        o[1] = p.y;
+        o[2] = p.z;
+    };
+    auto box = [&](int l, int64_t i, float *lo, float *hi) {
+        const int64_t o = lev_off_sh[l] + i;
+        lo[0] = nlo[o].x;
+        lo[1] = nlo[o].y;
+        lo[2] = nlo[o].z;
+        hi[0] = nhi[o].x;
+        hi[1] = nhi[o].y;
+        hi[2] = nhi[o].z;
+    };
+    for (int t = tid; t < kk; t += TREE_THREADS) {
+        const int j = (int)id[t];
+        float cj[3];
+        cent(t, cj);
+        const double *cjd = c + (int64_t)j * D;
+        double *cpj = c_prev + (int64_t)j * D;
+        const float dj = have_prev ? drift_bound<D>(cjd, cpj) : 0.0f;
+        const float s0 = nn_bound(have_prev != 0, have_prev ? cb_hi[j] : 0.0f, dj, dmax, e);
+        float sm = nn_search<D>(t, cj, s0, lev_size_sh, T.nlev, kk, cent, box);
+        if (!(sm < s0) && s0 < INFINITY) // nothing below the bound: search without it
+            sm = nn_search<D>(t, cj, INFINITY, lev_size_sh, T.nlev, kk, cent, box);
+        cb_lo[j] = dist_lo(sm, 2.0f * e);
+        cb_hi[j] = dist_hi(sm, 2.0f * e);
+        for (int i = 0; i < D; ++i)
+            cpj[i] = cjd[i];
+    }
 }
 
 // ------------------------------------------------------------------ large k
 template <int D>
 __global__ void __launch_bounds__(256) k_centroid_prep(const double *c, int64_t k, Grid g, float4 *c32,
-                                                       uint32_t *keys, int32_t *vals, unsigned *cmax_bits)
+                                                       uint32_t *keys, int32_t *vals, unsigned *cmax_bits,
+                                                       double *c_prev, float *drift, unsigned *drift_max,
+                                                       const int32_t *ctl)
 {
+    if (ctl[CTL_STOP])
+        return;
+    const int have_prev = ctl[CTL_STEPS] > 0;
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float nb = 0.0f;
+    float nb = 0.0f, dj = 0.0f;
     if (j < k) {
         float4 q4;
         uint32_t kb;
         nb = centroid_prep_one<D>(c, j, g, q4, kb);
         c32[j] = q4;
-        keys[j] = kb;
-        vals[j] = (int32_t)j;
+        if (keys) {
+            keys[j] = kb;
+            vals[j] = (int32_t)j;
+        }
+        if (c_prev) {
+            if (have_prev)
+                dj = drift_bound<D>(c + j * D, c_prev + j * D);
+            drift[j] = dj;
+            for (int i = 0; i < D; ++i)
+                c_prev[j * D + i] = c[j * D + i];
+        }
     }
     // non-negative floats order like their bit patterns
     float m = -wave_min_f32(-nb);
-    if (lane_id() == 0)
+    float dm = -wave_min_f32(-dj);
+    if (lane_id() == 0) {
         atomicMax(cmax_bits, __float_as_uint(m));
+        if (c_prev)
+            atomicMax(drift_max, __float_as_uint(dm));
+    }
+}
+
+// Inter bound of every centroid (large k): one thread per tree position,
+// nearest-neighbour search over the tree in global memory.
+template <int D>
+__global__ void __launch_bounds__(256) k_centroid_nn(TreeArgs T, int64_t k, const unsigned *cmax_bits,
+                                                     const float *drift, const unsigned *drift_max, float *cb_lo,
+                                                     float *cb_hi, const int32_t *ctl)
+{
+    if (ctl[CTL_STOP])
+        return;
+    const int have_prev = ctl[CTL_STEPS] > 0;
+    __shared__ int64_t lev_size_sh[TREE_MAX_LEVELS], lev_off_sh[TREE_MAX_LEVELS];
+    if (threadIdx.x < TREE_MAX_LEVELS) {
+        lev_size_sh[threadIdx.x] = T.lev_size[threadIdx.x];
+        lev_off_sh[threadIdx.x] = T.lev_off[threadIdx.x];
+    }
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k)
+        return;
+    const float e = err_of(__uint_as_float(*cmax_bits));
+    const float4 p = T.cs[t];
+    const int j = __float_as_int(p.w);
+    float cj[3] = {p.x, p.y, p.z};
+    auto cent = [&](int64_t q, float *o) {
+        const float4 v = T.cs[q];
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+    };
+    auto box = [&](int l, int64_t i, float *lo, float *hi) {
+        const int64_t o = lev_off_sh[l] + i;
+        f4_to3(T.node_lo[o], lo);
+        f4_to3(T.node_hi[o], hi);
+    };
+    const float s0 = nn_bound(have_prev != 0, have_prev ? cb_hi[j] : 0.0f, drift[j], __uint_as_float(*drift_max), e);
+    float sm = nn_search<D>(t, cj, s0, lev_size_sh, T.nlev, k, cent, box);
+    if (!(sm < s0) && s0 < INFINITY)
+        sm = nn_search<D>(t, cj, INFINITY, lev_size_sh, T.nlev, k, cent, box);
+    cb_lo[j] = dist_lo(sm, 2.0f * e);
+    cb_hi[j] = dist_hi(sm, 2.0f * e);
 }
 
 __global__ void __launch_bounds__(256) k_tree_buckets(const float4 *c32, const int32_t *sorted_id, int64_t k,
@@ -279,23 +499,27 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
     hipStream_t st = ctx->stream;
     const int64_t k = ctx->k;
     unsigned *cmax = (unsigned *)ctx->cerr;
+    const int32_t *hp = ctx->ctl;
     if (ctx->cfg.algo == KM_INDEXED && k <= SMALL_K) {
         if (ctx->d == 2)
             hipLaunchKernelGGL(k_tree_small<2>, dim3(1), dim3(TREE_THREADS), small_tree_lds(), st, c_in, k, ctx->grid,
-                               ctx->tree, ctx->c32, cmax);
+                               ctx->tree, ctx->c32, cmax, ctx->c_prev, ctx->cb_lo, ctx->cb_hi, hp);
         else
             hipLaunchKernelGGL(k_tree_small<3>, dim3(1), dim3(TREE_THREADS), small_tree_lds(), st, c_in, k, ctx->grid,
-                               ctx->tree, ctx->c32, cmax);
+                               ctx->tree, ctx->c32, cmax, ctx->c_prev, ctx->cb_lo, ctx->cb_hi, hp);
         return hip_ok(hipGetLastError(), "centroid tree launch") ? KM_OK : KM_ERR_HIP;
     }
     unsigned g = (unsigned)((k + 255) / 256);
+    const bool indexed = ctx->cfg.algo == KM_INDEXED;
+    uint32_t *keys = indexed ? ctx->ckey : nullptr;
+    double *cprev = indexed ? ctx->c_prev : nullptr;
     if (ctx->d == 2)
-        hipLaunchKernelGGL(k_centroid_prep<2>, dim3(g), dim3(256), 0, st, c_in, k, ctx->grid, ctx->c32, ctx->ckey,
-                           ctx->cval, cmax);
+        hipLaunchKernelGGL(k_centroid_prep<2>, dim3(g), dim3(256), 0, st, c_in, k, ctx->grid, ctx->c32, keys,
+                           ctx->cval, cmax, cprev, ctx->drift, ctx->drift_max, hp);
     else
-        hipLaunchKernelGGL(k_centroid_prep<3>, dim3(g), dim3(256), 0, st, c_in, k, ctx->grid, ctx->c32, ctx->ckey,
-                           ctx->cval, cmax);
-    if (ctx->cfg.algo != KM_INDEXED) // the brute path needs only fl32(c) and the norm bound
+        hipLaunchKernelGGL(k_centroid_prep<3>, dim3(g), dim3(256), 0, st, c_in, k, ctx->grid, ctx->c32, keys,
+                           ctx->cval, cmax, cprev, ctx->drift, ctx->drift_max, hp);
+    if (!indexed) // the brute path needs only fl32(c) and the norm bound
         return hip_ok(hipGetLastError(), "centroid prep launch") ? KM_OK : KM_ERR_HIP;
     bool in_tmp = false;
     if (!hip_ok(radix_sort_u32(ctx->ckey, ctx->cval, ctx->ckey2, ctx->cval2, k, key_bits(ctx->d), ctx->rs_hist,
@@ -308,6 +532,12 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
                        sid, k, T);
     for (int l = 1; l < T.nlev; ++l)
         hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.lev_size[l] + 255) / 256)), dim3(256), 0, st, T, l);
+    if (ctx->d == 2)
+        hipLaunchKernelGGL(k_centroid_nn<2>, dim3(g), dim3(256), 0, st, T, k, (const unsigned *)cmax,
+                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_lo, ctx->cb_hi, hp);
+    else
+        hipLaunchKernelGGL(k_centroid_nn<3>, dim3(g), dim3(256), 0, st, T, k, (const unsigned *)cmax,
+                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_lo, ctx->cb_hi, hp);
     return hip_ok(hipGetLastError(), "centroid tree launch") ? KM_OK : KM_ERR_HIP;
 }
 

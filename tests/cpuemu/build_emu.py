@@ -21,7 +21,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2412_02244_amd", "csrc")
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
-FLAGS = ["-std=c++17", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-ffp-contract=off",
+# -O0: a wave operation's call site is identified by its return address, and
+# an optimiser may duplicate code so that one source-level operation gets
+# two addresses (reported as a divergent wave operation that is not one).
+FLAGS = ["-std=c++17", "-O0", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-ffp-contract=off",
          "-Wno-unknown-pragmas", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-parameter",
          "-Wno-pass-failed"]
 

@@ -369,6 +369,13 @@ hipError_t hipMemsetAsync(void *p, int v, size_t bytes, hipStream_t)
     return hipSuccess;
 }
 hipError_t hipMemset(void *p, int v, size_t bytes) { return hipMemsetAsync(p, v, bytes, nullptr); }
+hipError_t hipMemsetD32Async(void *p, int v, size_t count, hipStream_t)
+{
+    int32_t *q = (int32_t *)p;
+    for (size_t i = 0; i < count; ++i)
+        q[i] = v;
+    return hipSuccess;
+}
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t bytes, hipMemcpyKind, hipStream_t)
 {
     memmove(dst, src, bytes);
@@ -416,3 +423,28 @@ hipError_t hipGetSymbolAddress(void **p, const void *sym)
     *p = const_cast<void *>(sym);
     return hipSuccess;
 }
+
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned)
+{
+    *s = malloc(8);
+    return hipSuccess;
+}
+hipError_t hipStreamDestroy(hipStream_t s)
+{
+    free(s);
+    return hipSuccess;
+}
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipErrorNotSupported; }
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g)
+{
+    *g = nullptr;
+    return hipErrorNotSupported;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t, hipGraphNode_t *, char *, size_t)
+{
+    *e = nullptr;
+    return hipErrorNotSupported;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }

@@ -164,7 +164,7 @@ T atomicCAS(T *p, T cmp, T v) { __atomic_compare_exchange_n(p, &cmp, v, false, _
 typedef int hipError_t;
 typedef void *hipStream_t;
 typedef void *hipEvent_t;
-enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1, hipErrorNotSupported = 801 };
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
 enum { hipHostMallocDefault = 0 };
 enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
@@ -179,6 +179,7 @@ hipError_t hipHostMalloc(void **p, size_t bytes, unsigned flags);
 hipError_t hipHostFree(void *p);
 hipError_t hipMemsetAsync(void *p, int v, size_t bytes, hipStream_t s = nullptr);
 hipError_t hipMemset(void *p, int v, size_t bytes);
+hipError_t hipMemsetD32Async(void *p, int v, size_t count, hipStream_t s = nullptr);
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t bytes, hipMemcpyKind, hipStream_t s = nullptr);
 hipError_t hipMemcpy(void *dst, const void *src, size_t bytes, hipMemcpyKind);
 hipError_t hipStreamSynchronize(hipStream_t);
@@ -195,5 +196,20 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipFuncSetAttribute(const void *f, hipFuncAttribute a, int v);
 hipError_t hipGetSymbolAddress(void **p, const void *sym);
 #define HIP_SYMBOL(x) (&(x))
+// streams and graphs: stream capture is not emulated (it reports an error,
+// so callers take their direct-launch path)
+typedef void *hipGraph_t;
+typedef void *hipGraphExec_t;
+typedef void *hipGraphNode_t;
+enum { hipStreamNonBlocking = 1 };
+enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal, hipStreamCaptureModeRelaxed };
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned flags);
+hipError_t hipStreamDestroy(hipStream_t s);
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode mode);
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g);
+hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t g, hipGraphNode_t *n, char *log, size_t len);
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
+hipError_t hipGraphDestroy(hipGraph_t g);
+hipError_t hipGraphExecDestroy(hipGraphExec_t e);
 
 #define hipLaunchKernelGGL(K, G, B, S, ST, ...) emu::launch(dim3(G), dim3(B), (size_t)(S), [=]() { K(__VA_ARGS__); })

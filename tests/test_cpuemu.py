@@ -28,7 +28,9 @@ KM_BRUTE, KM_INDEXED = 0, 1
 KM_FLAG_SSE = 1
 STATS = np.dtype([("n_changed", "<i8"), ("dist_evals", "<i8"), ("brute_evals", "<i8"),
                   ("single_cand_points", "<i8"), ("rechecked", "<i8"), ("cand_total", "<i8"),
-                  ("leaves", "<i8"), ("sse", "<f8")])
+                  ("leaves", "<i8"), ("sse", "<f8"), ("inter_leaf_points", "<i8"), ("inter_points", "<i8"),
+                  ("fallback_points", "<i8"), ("deferred_leaves", "<i8"), ("group_overflows", "<i8"),
+                  ("groups_skipped", "<i8")])
 
 
 @pytest.fixture(scope="module")
@@ -108,3 +110,33 @@ def test_emulated_run_until_stable(driver, tmp_path):
     assert it == ref["iters"]
     np.testing.assert_array_equal(a, ref["a"])
     np.testing.assert_array_equal(c, ref["c"])
+
+
+KM_FLAG_SMALL_LISTS = 4
+
+
+def test_emulated_fallback_paths(driver, tmp_path):
+    """Tiny candidate capacities: group overflow, deferred leaves and the
+    scan of all k centroids all run, and the trajectory is unchanged."""
+    x = geo_hotspots_2d(4000, n_hot=10, seed=81)
+    c0 = init_centroids(x, 90, 82)
+    ref = oracle.lloyd(x, c0, max_iter=3)
+    got = _run(driver, tmp_path, "kmeans", x, c0, 3, KM_INDEXED, 0, KM_FLAG_SSE | KM_FLAG_SMALL_LISTS)
+    for t, (a, c, st) in enumerate(got):
+        np.testing.assert_array_equal(a, ref["a_hist"][t])
+        np.testing.assert_array_equal(c, ref["c_hist"][t])
+    tot = {f: sum(int(st[f]) for _, _, st in got) for f in ("group_overflows", "deferred_leaves", "fallback_points")}
+    assert all(v > 0 for v in tot.values()), tot
+
+
+def test_emulated_long_trajectory_inter_bounds(driver, tmp_path):
+    """Ten steps: the exact sums are carried from step to step and moved
+    point by point or leaf by leaf, and the inter bounds keep leaves and
+    points; every step still equals the oracle."""
+    x = gaussian_mixture_2d(5000, seed=83).astype(np.float32)
+    c0 = init_centroids(x, 25, 84)
+    got = _check(driver, tmp_path, x, c0, 10, KM_INDEXED)
+    kept_leaf = sum(int(st["inter_leaf_points"]) for _, _, st in got[1:])
+    kept_pt = sum(int(st["inter_points"]) for _, _, st in got[1:])
+    assert kept_leaf > 0 and kept_pt > 0, (kept_leaf, kept_pt)
+    assert got[0][2]["inter_leaf_points"] == 0  # nothing is kept before the first assignment
