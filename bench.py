@@ -211,6 +211,35 @@ def leg_distortion(ekm, torch, dev) -> dict:
                          "FP64 accumulation", ms_per_fwd_bwd=round(per, 4), points_per_s=pts / (per * 1e-3))
 
 
+def leg_batched(ekm, torch, dev) -> dict:
+    from synth import batched_clouds
+    t0 = time.time()
+    x, po, c0, co = batched_clouds()
+    log(f"batched: {len(po) - 1} clouds, {x.shape[0]} points, {c0.shape[0]} centroids "
+        f"(generated in {time.time() - t0:.0f} s)")
+    xt = torch.from_numpy(x).to(dev)
+    c0t = torch.from_numpy(c0).to(dev)
+    iters = 30
+    c = c0t.clone()
+    tune_ms, (f, G) = gpu_ms(torch, lambda: ekm.kmeans_run_batched(xt, po, c, co, 1))
+    c = c0t.clone()
+    total_ms, _ = gpu_ms(torch, lambda: ekm.kmeans_run_batched(xt, po, c, co, iters))
+    init_ms, ctx = gpu_ms(torch, lambda: ekm.kmeans_init_batched(xt, po, co, leaf_size=f, cand_tile=G))
+    c = c0t.clone()
+    run_ms, (it, _) = gpu_ms(torch, lambda: ekm.kmeans_run(ctx, c, iters))
+    ctx.close()
+    n = x.shape[0]
+    per = run_ms / it
+    log(f"batched: leaf size {f}, leaves per list {G}; {per:.3f} ms/iteration, index build {init_ms:.1f} ms, "
+        f"kmeans_run_batched {total_ms:.1f} ms for {iters} iterations")
+    return dict(workload="4096 3D ellipsoid-surface clouds, sizes log-uniform in [1e3,1e5], k_i=n_i/100, "
+                         "indexed FP32 + FP64 recheck, 30 iterations, one context",
+                clouds=len(po) - 1, points=n, centroids=int(c0.shape[0]), iterations=it, leaf_size=f,
+                leaves_per_list=G, ms_per_iter=round(per, 4), value=n / (per * 1e-3),
+                index_build_ms=round(init_ms, 2), run_batched_ms=round(total_ms, 2),
+                run_batched_value=n * iters / (total_ms * 1e-3), first_call_with_tuning_ms=round(tune_ms, 2))
+
+
 def summarize_counters(fetch_csv: str, write_csv: str) -> dict:
     """HBM bytes per k_assign_waves launch from two rocprofv3 --pmc runs of
     `bench.py --quick --copy-calib` (FETCH_SIZE, then WRITE_SIZE, in KiB per
@@ -349,6 +378,7 @@ def main() -> int:
             f"(median of 2..T: {bms / (med_2T * 1e-3):.1f}x)")
         out["surfaces3d_1e7"] = leg_surfaces(ekm, torch, dev)
         out["distortion_256x16384"] = leg_distortion(ekm, torch, dev)
+        out["batched3d_4096"] = leg_batched(ekm, torch, dev)
     cpu = None
     if not args.no_cpu_baseline and not args.quick:
         log("CPU oracle baseline ...")

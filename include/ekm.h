@@ -84,9 +84,12 @@ typedef struct km_config {
     int32_t d;           /* point dimension: 2 or 3 */
     int32_t point_dtype; /* km_dtype of the points passed to kmeans_init */
     int32_t algo;        /* km_algo.  KM_INDEXED requires KM_F32 points. */
-    int32_t leaf_size;   /* f: maximum points per leaf, 0 = default (64); must be 0 or a
-                            power of two in [8, 64] */
-    int32_t cand_tile;   /* brute path: centroids staged in LDS per tile, 0 = default (1024) */
+    int32_t leaf_size;   /* f: maximum points per leaf, 0 = default (64; autotuned by
+                            kmeans_run_batched); must be 0 or a power of two in [8, 64] */
+    int32_t cand_tile;   /* indexed path: leaves sharing one candidate list (the tile of
+                            candidates staged in LDS), 1..8, 0 = default (8; autotuned by
+                            kmeans_run_batched); brute path: centroids staged in LDS per
+                            tile, 64..2048, 0 = default (1024) */
     uint32_t flags;      /* KM_FLAG_* */
     int64_t workspace_limit_bytes; /* 0 = unlimited; otherwise kmeans_init fails with
                                       KM_ERR_OOM if the workspace would exceed it */
@@ -159,6 +162,45 @@ EKM_API km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, in
  * per_iter asks for host data. */
 EKM_API km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t max_iter,
                      int32_t stop_when_stable, int32_t *iters_done, km_iter_stats *per_iter);
+
+/* A context over B independent clouds (the memory-tunable index of the
+ * paper's cost estimator, Eq. (12), applied to many small clouds at once):
+ * cloud b owns points [pt_offs[b], pt_offs[b+1]) of `points` (device, n x d
+ * FP32 row-major, n = pt_offs[B]) and centroids [c_offs[b], c_offs[b+1]) of
+ * the centroid arrays passed to kmeans_step / kmeans_run (k x d FP64, k =
+ * c_offs[B]).  Every cloud is clustered on its own: a point is assigned only
+ * among its cloud's centroids, and assignments returned in assign_out are
+ * cloud-local ids (0..k_b-1) in the caller's point order.  All clouds run in
+ * the same launches (one centroid-tree workgroup per cloud, one assignment
+ * launch over the leaves of all clouds).
+ *   pt_offs, c_offs: host arrays of B + 1 offsets starting at 0.
+ * Errors: KM_ERR_INVALID (null pointers, B < 1, offsets not starting at 0, a
+ * cloud with k_b < 1 or k_b > n_b, and the kmeans_init checks on the totals);
+ * KM_ERR_UNSUPPORTED (B > 1 with a cloud of more than 4096 centroids, or
+ * with KM_BRUTE); KM_ERR_NOT_EXACT; KM_ERR_OOM; KM_ERR_HIP.  B = 1 is the
+ * same as kmeans_init. */
+EKM_API km_status kmeans_init_batched(km_ctx **out, const km_config *cfg, const void *points,
+                              const int64_t *pt_offs, const int64_t *c_offs, int32_t B, void *stream);
+
+/* `iters` Lloyd iterations of B independent clouds (layout as for
+ * kmeans_init_batched), in one call: the index is built, the steps run in
+ * captured HIP graphs of several steps each, the assignment is written and the
+ * workspace released.
+ *   c_inout:    device, k x d FP64 (all clouds' centroids), refined in place.
+ *   assign_out: device, n int32 (cloud-local ids, caller order), or NULL.
+ *   cfg->leaf_size == 0 / cfg->cand_tile == 0: chosen by timing a few
+ *   iterations of each candidate (leaf sizes 16, 32, 64; 4 or 8 leaves per
+ *   candidate list) on up to 64 evenly spaced clouds; the choice is cached
+ *   per GPU architecture and workload class (d, typical cloud size and
+ *   centroid count) for the rest of the process.
+ *   tuned_out:  host int32[2] receiving the leaf size and the leaves per
+ *   candidate list used, or NULL.
+ * The stream is synchronised before returning.
+ * Errors: as kmeans_init_batched; KM_ERR_INVALID for null c_inout or iters < 0. */
+EKM_API km_status kmeans_run_batched(const void *points, const int64_t *pt_offs, double *c_inout,
+                             const int64_t *c_offs, int32_t *assign_out, int32_t B,
+                             const km_config *cfg, int32_t iters, void *stream,
+                             int32_t *tuned_out);
 
 /* GPU time per phase summed over the steps recorded since the previous call
  * (only steps of a context created with KM_FLAG_TIMING are recorded).

@@ -31,9 +31,11 @@ from ._binding import (  # noqa: F401
     distortion_fwd,
     kmeans_destroy,
     kmeans_init,
+    kmeans_init_batched,
     kmeans_last_error,
     kmeans_phase_times,
     kmeans_run,
+    kmeans_run_batched,
     kmeans_step,
     kmeans_step_times,
     kmeans_workspace_bytes,

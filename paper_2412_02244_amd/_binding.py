@@ -25,8 +25,8 @@ KM_FLAG_TIMING = 2
 KM_FLAG_SMALL_LISTS = 4
 PHASES = ("tree", "assign", "deferred", "update")
 
-EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy",
-            "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc",
+EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_init_batched", "kmeans_step", "kmeans_run",
+            "kmeans_run_batched", "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc",
             "kmeans_last_error")
 
 
@@ -69,6 +69,10 @@ def load_library(path: str = LIB_PATH):
     lib.kmeans_workspace_bytes.argtypes = [ctypes.POINTER(KmConfig), I64, I64]
     lib.kmeans_workspace_bytes.restype = ctypes.c_size_t
     lib.kmeans_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KmConfig), P, I64, I64, P]
+    lib.kmeans_init_batched.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KmConfig), P, ctypes.POINTER(I64),
+                                        ctypes.POINTER(I64), I32, P]
+    lib.kmeans_run_batched.argtypes = [P, ctypes.POINTER(I64), P, ctypes.POINTER(I64), P, I32,
+                                       ctypes.POINTER(KmConfig), I32, P, ctypes.POINTER(I32)]
     lib.kmeans_step.argtypes = [P, P, P, P, ctypes.POINTER(KmIterStats)]
     lib.kmeans_run.argtypes = [P, P, P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(KmIterStats)]
     lib.kmeans_destroy.argtypes = [P]
@@ -78,8 +82,9 @@ def load_library(path: str = LIB_PATH):
     lib.distortion_bwd.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.distortion_bwd_noalloc.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.kmeans_last_error.restype = ctypes.c_char_p
-    for name in ("kmeans_init", "kmeans_step", "kmeans_run", "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times",
-                 "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc"):
+    for name in ("kmeans_init", "kmeans_init_batched", "kmeans_run_batched", "kmeans_step", "kmeans_run",
+                 "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd",
+                 "distortion_bwd_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -151,6 +156,53 @@ def kmeans_init(points: torch.Tensor, k: int, algo: int = KM_INDEXED, leaf_size:
     _check(load_library().kmeans_init(ctypes.byref(h), ctypes.byref(cfg), _dev(points, "points"), n, k,
                                       _stream()))
     return Context(h.value, n, k, d)
+
+
+def _offsets(offs, name: str, B: int):
+    """Host int64 array of B + 1 offsets (a list, a tuple or a CPU tensor)."""
+    if isinstance(offs, torch.Tensor):
+        if offs.is_cuda:
+            raise ValueError(f"{name} must be host memory")
+        offs = offs.tolist()
+    offs = [int(v) for v in offs]
+    if len(offs) != B + 1:
+        raise ValueError(f"{name} must hold B + 1 = {B + 1} offsets, got {len(offs)}")
+    return (ctypes.c_int64 * len(offs))(*offs)
+
+
+def kmeans_init_batched(points: torch.Tensor, pt_offs, c_offs, algo: int = KM_INDEXED, leaf_size: int = 0,
+                        cand_tile: int = 0, flags: int = 0, workspace_limit_bytes: int = 0) -> Context:
+    """One context over B clouds: cloud b owns points ``pt_offs[b]:pt_offs[b+1]`` of ``points``
+    ([n, d] on the GPU) and centroids ``c_offs[b]:c_offs[b+1]`` of the centroid array."""
+    if points.dim() != 2:
+        raise ValueError("points must be [n, d]")
+    n, d = points.shape
+    B = len(pt_offs) - 1
+    po, co = _offsets(pt_offs, "pt_offs", B), _offsets(c_offs, "c_offs", B)
+    cfg = KmConfig(d, _pt_dtype(points), algo, leaf_size, cand_tile, flags, workspace_limit_bytes)
+    h = ctypes.c_void_p()
+    _check(load_library().kmeans_init_batched(ctypes.byref(h), ctypes.byref(cfg), _dev(points, "points"), po, co, B,
+                                              _stream()))
+    return Context(h.value, n, co[B], d)
+
+
+def kmeans_run_batched(points: torch.Tensor, pt_offs, c_inout: torch.Tensor, c_offs, iters: int,
+                       algo: int = KM_INDEXED, leaf_size: int = 0, cand_tile: int = 0,
+                       assign_out: torch.Tensor | None = None):
+    """``iters`` Lloyd iterations of every cloud, in place on ``c_inout``; returns the (f, G) used
+    (the tuned ones where ``leaf_size`` / ``cand_tile`` are 0)."""
+    if points.dim() != 2:
+        raise ValueError("points must be [n, d]")
+    d = points.shape[1]
+    B = len(pt_offs) - 1
+    po, co = _offsets(pt_offs, "pt_offs", B), _offsets(c_offs, "c_offs", B)
+    cfg = KmConfig(d, _pt_dtype(points), algo, leaf_size, cand_tile, 0, 0)
+    tuned = (ctypes.c_int32 * 2)()
+    _check(load_library().kmeans_run_batched(
+        _dev(points, "points"), po, _dev(c_inout, "c_inout", torch.float64), co,
+        None if assign_out is None else _dev(assign_out, "assign_out", torch.int32), B, ctypes.byref(cfg), iters,
+        _stream(), tuned))
+    return tuned[0], tuned[1]
 
 
 def kmeans_step(ctx: Context, c_in: torch.Tensor, c_out: torch.Tensor | None = None,

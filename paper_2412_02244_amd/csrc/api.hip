@@ -1,9 +1,11 @@
 // C ABI of libekm: argument checks, workspace, and the per-iteration
 // pipeline  A1 centroid tree -> A2 leaf candidates -> A3/A4 assignment with
 // fused exact accumulation -> A5 refinement (one pass of Algorithm 1's loop).
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
 
 #include "ekm_internal.hpp"
@@ -68,8 +70,12 @@ static km_status check_config(const km_config *cfg, int64_t n, int64_t k)
         return KM_ERR_INVALID;
     }
     int t = cfg->cand_tile;
-    if (t != 0 && (t < 64 || t > 2048)) {
-        set_error("cand_tile must be 0 or in [64, 2048]");
+    if (cfg->algo == KM_INDEXED && t != 0 && (t < 1 || t > GROUP_LEAVES)) {
+        set_error("cand_tile (indexed: leaves sharing one candidate list) must be 0 or in [1, 8]");
+        return KM_ERR_INVALID;
+    }
+    if (cfg->algo == KM_BRUTE && t != 0 && (t < 64 || t > 2048)) {
+        set_error("cand_tile (brute: centroids per LDS tile) must be 0 or in [64, 2048]");
         return KM_ERR_INVALID;
     }
     if (cfg->algo == KM_INDEXED && cfg->point_dtype != KM_F32) {
@@ -328,6 +334,9 @@ km_status kmeans_destroy(km_ctx *ctx)
         hipHostFree(ctx->host_stat);
     if (ctx->host_ctl)
         hipHostFree(ctx->host_ctl);
+    for (auto e : ctx->chunk_ev)
+        if (e)
+            hipEventDestroy(e);
     if (ctx->stat_hist)
         hipFree(ctx->stat_hist);
     if (ctx->chunk_exec)
@@ -338,20 +347,12 @@ km_status kmeans_destroy(km_ctx *ctx)
     return KM_OK;
 }
 
-km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, int64_t n, int64_t k, void *stream)
+// Context over B clouds (B = 1: kmeans_init) with point / centroid offsets
+// pt_off / c_off ([B + 1], host), already validated.
+static km_status init_context(km_ctx **out, const km_config *cfg, const void *points, int B, const int64_t *pt_off,
+                              const int64_t *c_off, void *stream)
 {
-    if (!out) {
-        set_error("kmeans_init: null output pointer");
-        return KM_ERR_INVALID;
-    }
-    *out = nullptr;
-    km_status s = check_config(cfg, n, k);
-    if (s != KM_OK)
-        return s;
-    if (!points) {
-        set_error("kmeans_init: null points");
-        return KM_ERR_INVALID;
-    }
+    const int64_t n = pt_off[B], k = c_off[B];
     if (cfg->workspace_limit_bytes > 0 && workspace_bytes(cfg, n, k) > (size_t)cfg->workspace_limit_bytes) {
         set_error("kmeans_init: workspace of " + std::to_string(workspace_bytes(cfg, n, k)) +
                   " bytes exceeds workspace_limit_bytes");
@@ -369,17 +370,35 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
     ctx->k = k;
     ctx->d = cfg->d;
     ctx->f = cfg->leaf_size ? cfg->leaf_size : 64;
-    ctx->tile = cfg->cand_tile ? cfg->cand_tile : 1024;
+    ctx->G = cfg->algo == KM_INDEXED && cfg->cand_tile ? cfg->cand_tile : GROUP_LEAVES;
+    ctx->tile = cfg->algo == KM_BRUTE && cfg->cand_tile ? cfg->cand_tile : 1024;
     ctx->stream = (hipStream_t)stream;
     ctx->small_lists = (cfg->flags & KM_FLAG_SMALL_LISTS) ? 1 : 0;
     hipGetDevice(&ctx->device);
+    hipStream_t st = ctx->stream;
+    km_status s;
+    ctx->B = B;
+    ctx->h_pt_off.assign(pt_off, pt_off + B + 1);
+    ctx->h_c_off.assign(c_off, c_off + B + 1);
+    ctx->pt_off = ctx_alloc<int64_t>(ctx, B + 1);
+    ctx->c_off = ctx_alloc<int64_t>(ctx, B + 1);
+    if (!ctx->pt_off || !ctx->c_off) {
+        kmeans_destroy(ctx);
+        return alloc_fail(nullptr);
+    }
+    if (!hip_ok(hipMemcpyAsync(ctx->pt_off, pt_off, (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync") ||
+        !hip_ok(hipMemcpyAsync(ctx->c_off, c_off, (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync")) {
+        kmeans_destroy(ctx);
+        return KM_ERR_HIP;
+    }
 
     s = build_leaves(ctx, points);
     if (s != KM_OK) {
         kmeans_destroy(ctx);
         return s;
     }
-    hipStream_t st = ctx->stream;
     const int64_t L = ctx->L;
     ctx->a = ctx_alloc<int32_t>(ctx, n);
     ctx->c32 = ctx_alloc<float4>(ctx, k);
@@ -399,20 +418,60 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
         return alloc_fail(nullptr);
     }
     if (cfg->algo == KM_INDEXED) {
-        TreeArgs &T = ctx->tree;
-        tree_layout(k, T);
-        T.cs = ctx_alloc<float4>(ctx, k);
-        T.node_lo = ctx_alloc<float4>(ctx, T.nnodes);
-        T.node_hi = ctx_alloc<float4>(ctx, T.nnodes);
+        // one tree per cloud, in concatenated arrays (tree positions local,
+        // ids global), and the chunks of the inter-bound pair scan
+        ctx->h_trees.assign(B, TreeArgs{});
+        int64_t nn = 0;
+        std::vector<int32_t> chunk_cloud, chunk_first;
+        for (int b = 0; b < B; ++b) {
+            TreeArgs &T = ctx->h_trees[b];
+            T.k = c_off[b + 1] - c_off[b];
+            T.c0 = c_off[b];
+            tree_layout(T.k, T);
+            nn += T.nnodes;
+            for (int64_t j = 0; j < T.k; j += WAVE) {
+                chunk_cloud.push_back(b);
+                chunk_first.push_back((int32_t)(T.c0 + j));
+            }
+        }
+        float4 *cs = ctx_alloc<float4>(ctx, k), *nlo = ctx_alloc<float4>(ctx, nn), *nhi = ctx_alloc<float4>(ctx, nn);
+        ctx->trees = ctx_alloc<TreeArgs>(ctx, B);
+        ctx->ncb_chunks = (int64_t)chunk_cloud.size();
+        ctx->cb_chunk_cloud = ctx_alloc<int32_t>(ctx, ctx->ncb_chunks);
+        ctx->cb_chunk_first = ctx_alloc<int32_t>(ctx, ctx->ncb_chunks);
+        if (!cs || !nlo || !nhi || !ctx->trees || !ctx->cb_chunk_cloud || !ctx->cb_chunk_first) {
+            kmeans_destroy(ctx);
+            return alloc_fail(nullptr);
+        }
+        for (int b = 0, no = 0; b < B; ++b) {
+            TreeArgs &T = ctx->h_trees[b];
+            T.cs = cs + T.c0;
+            T.node_lo = nlo + no;
+            T.node_hi = nhi + no;
+            no += (int)T.nnodes;
+        }
+        ctx->tree = ctx->h_trees[0];
+        if (!hip_ok(hipMemcpyAsync(ctx->trees, ctx->h_trees.data(), B * sizeof(TreeArgs), hipMemcpyHostToDevice, st),
+                    "hipMemcpyAsync") ||
+            !hip_ok(hipMemcpyAsync(ctx->cb_chunk_cloud, chunk_cloud.data(), chunk_cloud.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st),
+                    "hipMemcpyAsync") ||
+            !hip_ok(hipMemcpyAsync(ctx->cb_chunk_first, chunk_first.data(), chunk_first.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st),
+                    "hipMemcpyAsync") ||
+            !hip_ok(hipStreamSynchronize(st), "hipStreamSynchronize")) { // the host vectors go out of scope
+            kmeans_destroy(ctx);
+            return KM_ERR_HIP;
+        }
         ctx->leaf_own = ctx_alloc<int32_t>(ctx, L);
         ctx->heavy = ctx_alloc<int32_t>(ctx, L);
         ctx->heavy_cnt = ctx_alloc<int32_t>(ctx, 1);
-        ctx->cb_lo = ctx_alloc<float>(ctx, k);
+        ctx->cb_s = ctx_alloc<unsigned>(ctx, k);
         ctx->cb_hi = ctx_alloc<float>(ctx, k);
         ctx->drift = ctx_alloc<float>(ctx, k);
         ctx->drift_max = ctx_alloc<unsigned>(ctx, 1);
         ctx->c_prev = ctx_alloc<double>(ctx, (size_t)k * ctx->d);
-        if (!T.cs || !T.node_lo || !T.node_hi || !ctx->leaf_own || !ctx->heavy || !ctx->heavy_cnt || !ctx->cb_lo ||
+        if (!ctx->leaf_own || !ctx->heavy || !ctx->heavy_cnt || !ctx->cb_s ||
             !ctx->cb_hi || !ctx->drift || !ctx->drift_max || !ctx->c_prev) {
             kmeans_destroy(ctx);
             return alloc_fail(nullptr);
@@ -431,11 +490,18 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
         kmeans_destroy(ctx);
         return alloc_fail(nullptr);
     }
-    if (hipHostMalloc((void **)&ctx->host_ctl, CTL_N * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&ctx->host_ctl, (RUN_AHEAD + 1) * CTL_N * sizeof(int32_t), hipHostMallocDefault) !=
+        hipSuccess) {
         ctx->host_ctl = nullptr;
         kmeans_destroy(ctx);
         return alloc_fail(nullptr);
     }
+    for (auto &e : ctx->chunk_ev)
+        if (!hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "kmeans_init: hipEventCreate")) {
+            e = nullptr;
+            kmeans_destroy(ctx);
+            return KM_ERR_HIP;
+        }
     if (hipHostMalloc((void **)&ctx->host_stat, (NSTAT + 1) * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
         ctx->host_stat = nullptr;
         kmeans_destroy(ctx);
@@ -458,6 +524,77 @@ km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, in
     }
     *out = ctx;
     return KM_OK;
+}
+
+km_status kmeans_init(km_ctx **out, const km_config *cfg, const void *points, int64_t n, int64_t k, void *stream)
+{
+    if (!out) {
+        set_error("kmeans_init: null output pointer");
+        return KM_ERR_INVALID;
+    }
+    *out = nullptr;
+    km_status s = check_config(cfg, n, k);
+    if (s != KM_OK)
+        return s;
+    if (!points) {
+        set_error("kmeans_init: null points");
+        return KM_ERR_INVALID;
+    }
+    const int64_t pt_off[2] = {0, n}, c_off[2] = {0, k};
+    return init_context(out, cfg, points, 1, pt_off, c_off, stream);
+}
+
+// Checks of a batched call's arguments (before any GPU work).
+static km_status check_batch(const km_config *cfg, const void *points, const int64_t *pt_offs,
+                             const int64_t *c_offs, int32_t B)
+{
+    if (!cfg || !points || !pt_offs || !c_offs) {
+        set_error("batched: null argument");
+        return KM_ERR_INVALID;
+    }
+    if (B < 1) {
+        set_error("batched: B must be >= 1");
+        return KM_ERR_INVALID;
+    }
+    if (pt_offs[0] != 0 || c_offs[0] != 0) {
+        set_error("batched: pt_offs[0] and c_offs[0] must be 0");
+        return KM_ERR_INVALID;
+    }
+    for (int b = 0; b < B; ++b) {
+        const int64_t nb = pt_offs[b + 1] - pt_offs[b], kb = c_offs[b + 1] - c_offs[b];
+        if (nb < 1 || kb < 1 || kb > nb) {
+            set_error("batched: cloud " + std::to_string(b) + " needs 1 <= k_b <= n_b (got n_b = " +
+                      std::to_string(nb) + ", k_b = " + std::to_string(kb) + ")");
+            return KM_ERR_INVALID;
+        }
+        if (B > 1 && kb > TREE_SMALL_K) {
+            set_error("batched: cloud " + std::to_string(b) + " has more than " + std::to_string(TREE_SMALL_K) +
+                      " centroids (one workgroup builds each cloud's tree)");
+            return KM_ERR_UNSUPPORTED;
+        }
+    }
+    km_status s = check_config(cfg, pt_offs[B], c_offs[B]);
+    if (s != KM_OK)
+        return s;
+    if (B > 1 && cfg->algo != KM_INDEXED) {
+        set_error("batched: several clouds need KM_INDEXED");
+        return KM_ERR_UNSUPPORTED;
+    }
+    return KM_OK;
+}
+
+km_status kmeans_init_batched(km_ctx **out, const km_config *cfg, const void *points, const int64_t *pt_offs,
+                              const int64_t *c_offs, int32_t B, void *stream)
+{
+    if (!out) {
+        set_error("kmeans_init_batched: null output pointer");
+        return KM_ERR_INVALID;
+    }
+    *out = nullptr;
+    km_status s = check_batch(cfg, points, pt_offs, c_offs, B);
+    if (s != KM_OK)
+        return s;
+    return init_context(out, cfg, points, B, pt_offs, c_offs, stream);
 }
 
 km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, km_iter_stats *stats)
@@ -516,10 +653,15 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
     }
     // The steps are launched in chunks without waiting for them; the device
     // counts them and stops the run (every later kernel returns at once)
-    // after max_iter steps or at the first stable step.  The host looks at
-    // the device only between chunks, and only when the run may stop early.
+    // after max_iter steps or at the first stable step.  When the run may
+    // stop early, a copy of the control block is taken after every chunk and
+    // the host looks at the copy of a chunk only once RUN_AHEAD later chunks
+    // are queued, so the device never waits for the host; at most RUN_AHEAD
+    // chunks of steps that return at once follow the end of the run.
     km_status s = set_ctl(ctx, max_iter, stop_when_stable ? 1 : 0, 0);
     const bool timing = (ctx->cfg.flags & KM_FLAG_TIMING) != 0;
+    int queued = 0; // chunks whose control copies are not yet looked at
+    int nchunk = 0;
     for (int launched = 0; s == KM_OK && launched < max_iter;) {
         const int chunk = max_iter - launched < RUN_CHUNK ? max_iter - launched : RUN_CHUNK;
         if (!timing && chunk == RUN_CHUNK && chunk_graph(ctx, c_inout)) {
@@ -530,24 +672,38 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
                 s = timed_step(ctx, c_inout, c_inout, nullptr);
         }
         launched += chunk;
-        if (s == KM_OK && stop_when_stable && launched < max_iter) {
-            if (!hip_ok(hipMemcpyAsync(ctx->host_ctl, ctx->ctl, CTL_N * sizeof(int32_t), hipMemcpyDeviceToHost, st),
-                        "kmeans_run: control copy") ||
-                !hip_ok(hipStreamSynchronize(st), "kmeans_run: hipStreamSynchronize"))
+        if (s != KM_OK || !stop_when_stable || launched >= max_iter)
+            continue;
+        const int slot = nchunk % RUN_AHEAD;
+        if (queued == RUN_AHEAD) { // the oldest copy in the ring is about to be reused: look at it
+            if (!hip_ok(hipEventSynchronize(ctx->chunk_ev[slot]), "kmeans_run: hipEventSynchronize")) {
                 s = KM_ERR_HIP;
-            else if (ctx->host_ctl[CTL_STOP])
+                continue;
+            }
+            --queued;
+            if (ctx->host_ctl[slot * CTL_N + CTL_STOP])
                 break;
         }
+        if (!hip_ok(hipMemcpyAsync(ctx->host_ctl + slot * CTL_N, ctx->ctl, CTL_N * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, st),
+                    "kmeans_run: control copy") ||
+            !hip_ok(hipEventRecord(ctx->chunk_ev[slot], st), "kmeans_run: hipEventRecord")) {
+            s = KM_ERR_HIP;
+            continue;
+        }
+        ++queued;
+        ++nchunk;
     }
     if (s != KM_OK) {
         (void)set_ctl(ctx, 0, 0, 1);
         return s;
     }
-    if (!hip_ok(hipMemcpyAsync(ctx->host_ctl, ctx->ctl, CTL_N * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+    int32_t *final_ctl = ctx->host_ctl + RUN_AHEAD * CTL_N;
+    if (!hip_ok(hipMemcpyAsync(final_ctl, ctx->ctl, CTL_N * sizeof(int32_t), hipMemcpyDeviceToHost, st),
                 "kmeans_run: control copy") ||
         !hip_ok(hipStreamSynchronize(st), "kmeans_run: hipStreamSynchronize"))
         return KM_ERR_HIP;
-    const int32_t iters = ctx->host_ctl[CTL_RUN_ITERS];
+    const int32_t iters = final_ctl[CTL_RUN_ITERS];
     if ((s = set_ctl(ctx, 0, 0, 1)) != KM_OK) // back to single steps
         return s;
     ctx->steps_done += iters;
@@ -564,6 +720,161 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
     if (iters_done)
         *iters_done = iters;
     return KM_OK;
+}
+
+// Leaf size and leaves per candidate list for a batched run (f, G): the
+// given ones, or the fastest of the candidates over 3 timed iterations
+// (after one warm-up iteration) on up to 64 evenly spaced clouds.  Cached
+// per GPU architecture and workload class.
+static km_status autotune(const km_config *cfg, const void *points, const int64_t *pt_offs, const double *c,
+                          const int64_t *c_offs, int B, hipStream_t st, int &f_out, int &G_out)
+{
+    std::vector<int> fs, Gs;
+    if (cfg->leaf_size)
+        fs.push_back(cfg->leaf_size);
+    else
+        fs = {16, 32, 64};
+    if (cfg->cand_tile)
+        Gs.push_back(cfg->cand_tile);
+    else
+        Gs = {4, 8};
+    f_out = fs[0];
+    G_out = Gs[0];
+    if (fs.size() * Gs.size() == 1)
+        return KM_OK;
+    static std::mutex mu;
+    static std::map<std::string, std::pair<int, int>> cache;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (!hip_ok(hipGetDevice(&dev), "autotune: hipGetDevice") ||
+        !hip_ok(hipGetDeviceProperties(&prop, dev), "autotune: hipGetDeviceProperties"))
+        return KM_ERR_HIP;
+    auto lg = [](double v) { return (int)std::lround(std::log2(v > 1.0 ? v : 1.0)); };
+    const std::string key = std::string(prop.gcnArchName) + "/d" + std::to_string(cfg->d) + "/n" +
+                            std::to_string(lg((double)pt_offs[B] / B)) + "/k" +
+                            std::to_string(lg((double)c_offs[B] / B)) + "/f" + std::to_string(cfg->leaf_size) +
+                            "/t" + std::to_string(cfg->cand_tile);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            f_out = it->second.first;
+            G_out = it->second.second;
+            return KM_OK;
+        }
+    }
+    // the sample: clouds floor(i B / S), copied into their own arrays
+    const int S = B < 64 ? B : 64;
+    const int d = cfg->d;
+    std::vector<int64_t> spt(S + 1, 0), sco(S + 1, 0);
+    std::vector<int> pick(S);
+    for (int i = 0; i < S; ++i) {
+        pick[i] = (int)((int64_t)i * B / S);
+        spt[i + 1] = spt[i] + (pt_offs[pick[i] + 1] - pt_offs[pick[i]]);
+        sco[i + 1] = sco[i] + (c_offs[pick[i] + 1] - c_offs[pick[i]]);
+    }
+    float *pts = nullptr;
+    double *cs = nullptr, *ct = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    km_status s = KM_OK;
+    if (hipMalloc((void **)&pts, (size_t)spt[S] * d * sizeof(float)) != hipSuccess ||
+        hipMalloc((void **)&cs, (size_t)sco[S] * d * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&ct, (size_t)sco[S] * d * sizeof(double)) != hipSuccess) {
+        set_error("autotune: device allocation failed");
+        s = KM_ERR_OOM;
+    }
+    if (s == KM_OK && (!hip_ok(hipEventCreate(&e0), "autotune: hipEventCreate") ||
+                       !hip_ok(hipEventCreate(&e1), "autotune: hipEventCreate")))
+        s = KM_ERR_HIP;
+    for (int i = 0; s == KM_OK && i < S; ++i) {
+        const int b = pick[i];
+        if (!hip_ok(hipMemcpyAsync(pts + spt[i] * d, (const float *)points + pt_offs[b] * d,
+                                   (size_t)(pt_offs[b + 1] - pt_offs[b]) * d * sizeof(float), hipMemcpyDeviceToDevice,
+                                   st),
+                    "autotune: copy") ||
+            !hip_ok(hipMemcpyAsync(cs + sco[i] * d, c + c_offs[b] * d,
+                                   (size_t)(c_offs[b + 1] - c_offs[b]) * d * sizeof(double), hipMemcpyDeviceToDevice,
+                                   st),
+                    "autotune: copy"))
+            s = KM_ERR_HIP;
+    }
+    float best = INFINITY;
+    for (size_t a = 0; s == KM_OK && a < fs.size(); ++a)
+        for (size_t g = 0; s == KM_OK && g < Gs.size(); ++g) {
+            km_config c2 = *cfg;
+            c2.leaf_size = fs[a];
+            c2.cand_tile = Gs[g];
+            c2.flags &= ~(KM_FLAG_TIMING | KM_FLAG_SSE | KM_FLAG_SMALL_LISTS);
+            c2.workspace_limit_bytes = 0;
+            km_ctx *ctx = nullptr;
+            if ((s = init_context(&ctx, &c2, pts, S, spt.data(), sco.data(), st)) != KM_OK)
+                break;
+            float ms = 0.0f;
+            if (!hip_ok(hipMemcpyAsync(ct, cs, (size_t)sco[S] * d * sizeof(double), hipMemcpyDeviceToDevice, st),
+                        "autotune: copy") ||
+                (s = kmeans_run(ctx, ct, nullptr, 1, 0, nullptr, nullptr)) != KM_OK ||
+                !hip_ok(hipEventRecord(e0, st), "autotune: hipEventRecord") ||
+                (s = kmeans_run(ctx, ct, nullptr, 3, 0, nullptr, nullptr)) != KM_OK ||
+                !hip_ok(hipEventRecord(e1, st), "autotune: hipEventRecord") ||
+                !hip_ok(hipEventSynchronize(e1), "autotune: hipEventSynchronize") ||
+                !hip_ok(hipEventElapsedTime(&ms, e0, e1), "autotune: hipEventElapsedTime"))
+                s = s == KM_OK ? KM_ERR_HIP : s;
+            kmeans_destroy(ctx);
+            if (s == KM_OK && ms < best) {
+                best = ms;
+                f_out = fs[a];
+                G_out = Gs[g];
+            }
+        }
+    if (e0)
+        hipEventDestroy(e0);
+    if (e1)
+        hipEventDestroy(e1);
+    if (pts)
+        hipFree(pts);
+    if (cs)
+        hipFree(cs);
+    if (ct)
+        hipFree(ct);
+    if (s == KM_OK) {
+        std::lock_guard<std::mutex> lock(mu);
+        cache[key] = {f_out, G_out};
+    }
+    return s;
+}
+
+km_status kmeans_run_batched(const void *points, const int64_t *pt_offs, double *c_inout, const int64_t *c_offs,
+                             int32_t *assign_out, int32_t B, const km_config *cfg, int32_t iters, void *stream,
+                             int32_t *tuned_out)
+{
+    km_status s = check_batch(cfg, points, pt_offs, c_offs, B);
+    if (s != KM_OK)
+        return s;
+    if (!c_inout || iters < 0) {
+        set_error("kmeans_run_batched: null c_inout or iters < 0");
+        return KM_ERR_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    km_config c2 = *cfg;
+    if (cfg->algo == KM_INDEXED) {
+        int f = 0, G = 0;
+        if ((s = autotune(cfg, points, pt_offs, c_inout, c_offs, B, st, f, G)) != KM_OK)
+            return s;
+        c2.leaf_size = f;
+        c2.cand_tile = G;
+    }
+    km_ctx *ctx = nullptr;
+    if ((s = init_context(&ctx, &c2, points, B, pt_offs, c_offs, stream)) != KM_OK)
+        return s;
+    s = kmeans_run(ctx, c_inout, assign_out, iters, 0, nullptr, nullptr);
+    if (s == KM_OK && !hip_ok(hipStreamSynchronize(st), "kmeans_run_batched: hipStreamSynchronize"))
+        s = KM_ERR_HIP;
+    if (s == KM_OK && tuned_out) {
+        tuned_out[0] = ctx->f;
+        tuned_out[1] = ctx->G;
+    }
+    kmeans_destroy(ctx);
+    return s;
 }
 
 } // extern "C"

@@ -31,6 +31,7 @@ constexpr int G_WAVES = ASSIGN_THREADS / WAVE; // independent waves per workgrou
 // per-leaf pass, whose waves have room for crowded leaves (one workgroup
 // per CU there).
 constexpr int SW_MAIN = 256, FR_MAIN = 1024;
+static_assert(HEAVY_M >= SW_MAIN, "no leaf is deferred for its candidate count alone (see HEAVY_M)");
 constexpr int SW_HEAVY = 1024, FR_HEAVY = 4096;
 static_assert(GROUP_LEAVES <= WAVE, "one lane holds one leaf of the group");
 static_assert(TREE_START_MAX <= FR_MAIN && TREE_START_MAX <= FR_HEAVY, "the first descent level fits");
@@ -43,7 +44,7 @@ struct AssignArgs {
     const double *c_in; // [k][d]
     const float4 *c32;  // [k]
     const unsigned *cmax_bits;
-    const float *cb_lo; // [k] lower bound on the distance from c_j to its nearest other centroid
+    const float *cb_s;  // [k] smallest FP32 squared distance from fl32(c_j) to another fl32 centroid
     // leaves and groups
     const int32_t *leaf_start;
     int64_t L;
@@ -55,8 +56,9 @@ struct AssignArgs {
     const int32_t *group_leaf;
     const float4 *group_box;
     int64_t ngroups;
-    // centroid tree
-    TreeArgs T;
+    // centroid trees (one per cloud) and the cloud of each group and leaf
+    const TreeArgs *trees;
+    const int32_t *group_cloud, *leaf_cloud;
     // exact sums
     int S;
     int fix64;
@@ -186,10 +188,10 @@ __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 // holds a centroid).  Each lane keeps the min-distances of its entries in
 // its own LDS slots between the two passes of a level.
 template <int D, class WS>
-__device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A, float e, WS &sh, int sw, int fr)
+__device__ int wave_search(const float *lo, const float *hi, const TreeArgs *Tp, float e, WS &sh, int sw, int fr)
 {
     const int npar = fr / TREE_BUCKET;
-    const TreeArgs &T = A.T;
+    const TreeArgs &T = *Tp; // the cloud's tree (read through the pointer: no register copy)
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
     wave_sync(); // earlier readers of sh are done
@@ -244,7 +246,7 @@ __device__ int wave_search(const float *lo, const float *hi, const AssignArgs &A
     for (int i = lane; i < F; i += WAVE) {
         const int64_t t = (int64_t)sh.par[cur][i / TREE_BUCKET] * TREE_BUCKET + i % TREE_BUCKET;
         float m = INFINITY;
-        if (t < A.k) {
+        if (t < T.k) {
             float cc[3];
             f4_to(T.cs[t], cc);
             m = box_mind<D>(lo, hi, cc);
@@ -366,12 +368,13 @@ __device__ inline void leaf_sum_add(const AssignArgs &A, int64_t l, int key, int
     }
 }
 
+// Canonical FP64 argmin over centroids [j0, j1) (lowest index on ties).
 template <int D>
-__device__ inline int brute64_all(const double (&xd)[D], const AssignArgs &A)
+__device__ inline int brute64_all(const double (&xd)[D], const AssignArgs &A, int64_t j0, int64_t j1)
 {
     double best = INFINITY;
-    int bj = 0;
-    for (int64_t j = 0; j < A.k; ++j) {
+    int bj = (int)j0;
+    for (int64_t j = j0; j < j1; ++j) {
         double Dv = sqdist64<D>(xd, A.c_in + j * D);
         if (Dv < best) {
             best = Dv;
@@ -564,18 +567,20 @@ __device__ inline int assign_point(const float (&x)[D], bool need, const float *
 // rule, canonical FP64 brute force for the lanes that need it.  For leaves
 // whose candidate list does not fit anywhere.
 template <int D>
-__device__ inline int scan_all(const float (&x)[D], bool need, float e, const AssignArgs &A, int64_t (&st)[NSTAT])
+__device__ inline int scan_all(const float (&x)[D], bool need, float e, const AssignArgs &A, const TreeArgs *Tp,
+                               int64_t (&st)[NSTAT])
 {
     const int lane = lane_id();
+    const int64_t c0 = Tp->c0, c1 = Tp->c0 + Tp->k; // the cloud's centroids
     Best2 bs[SCAN_ILP];
 #pragma unroll
     for (int u = 0; u < SCAN_ILP; ++u)
         bs[u] = best2_init();
-    float4 cur = lane < A.k ? A.c32[lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int64_t j0 = 0; j0 < A.k; j0 += WAVE) {
+    float4 cur = c0 + lane < c1 ? A.c32[c0 + lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int64_t j0 = c0; j0 < c1; j0 += WAVE) {
         const int64_t jn = j0 + WAVE + lane;
-        const float4 nxt = jn < A.k ? A.c32[jn] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const int cn = (int)(A.k - j0 < WAVE ? A.k - j0 : WAVE);
+        const float4 nxt = jn < c1 ? A.c32[jn] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const int cn = (int)(c1 - j0 < WAVE ? c1 - j0 : WAVE);
         for (int b0 = 0; b0 < cn; b0 += SCAN_ILP) {
 #pragma unroll
             for (int u = 0; u < SCAN_ILP; ++u) {
@@ -600,7 +605,7 @@ __device__ inline int scan_all(const float (&x)[D], bool need, float e, const As
         double xd[D];
         for (int i = 0; i < D; ++i)
             xd[i] = (double)x[i];
-        best = brute64_all<D>(xd, A);
+        best = brute64_all<D>(xd, A, c0, c1);
     }
     return best;
 }
@@ -721,7 +726,7 @@ __device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafP
     if (J.own >= 0) {
         float cc[3];
         f4_to(A.c32[J.own], cc);
-        pk = valid && inter_keep(A.cb_lo[J.own], sqdist32<D>(P.x, cc), e);
+        pk = valid && inter_keep(A.cb_s[J.own], sqdist32<D>(P.x, cc), e);
         st[ST_KEEP_PTS] += wave_count(pk);
     }
     const bool need = valid && !pk;
@@ -751,11 +756,11 @@ __device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafP
 
 // A leaf whose candidate list does not fit: every point scans all k.
 template <int D>
-__device__ void leaf_all(const AssignArgs &A, const LeafJob &J, float e, int64_t (&st)[NSTAT])
+__device__ void leaf_all(const AssignArgs &A, const LeafJob &J, float e, const TreeArgs *Tp, int64_t (&st)[NSTAT])
 {
     const LeafPts<D> P = load_pts<D>(A, J);
-    decide_points<D>(A, J, P, e, A.k,
-                     [&](const float (&x)[D], bool need) { return scan_all<D>(x, need, e, A, st); }, st);
+    decide_points<D>(A, J, P, e, Tp->k,
+                     [&](const float (&x)[D], bool need) { return scan_all<D>(x, need, e, A, Tp, st); }, st);
 }
 
 // Whether a leaf's decision reads its points (m: its candidate count).
@@ -768,10 +773,10 @@ __device__ inline bool needs_points(int m, int own, int j1, int heavy_m)
 // points when needs_points() (loaded ahead by the caller).
 template <int D, class WS>
 __device__ void leaf_listed(const AssignArgs &A, const LeafJob &J, int m, int j1, float thr, int sn, float e,
-                            const WS &sh, const LeafPts<D> &P, int64_t (&st)[NSTAT])
+                            const WS &sh, const LeafPts<D> &P, const TreeArgs *Tp, int64_t (&st)[NSTAT])
 {
     if (m == 0) { // cannot happen for a well-formed tree; stay correct regardless
-        leaf_all<D>(A, J, e, st);
+        leaf_all<D>(A, J, e, Tp, st);
         return;
     }
     st[ST_CANDS] += m;
@@ -790,16 +795,16 @@ __device__ void leaf_listed(const AssignArgs &A, const LeafJob &J, int m, int j1
 // capacities sw / fr; returns false if the list does not fit.
 template <int D, class WS>
 __device__ bool leaf_searched(const AssignArgs &A, const LeafJob &J, float e, WS &sh, int sw, int fr,
-                              int64_t (&st)[NSTAT])
+                              const TreeArgs *Tp, int64_t (&st)[NSTAT])
 {
-    const int sn = wave_search<D>(J.lo, J.hi, A, e, sh, sw, fr);
+    const int sn = wave_search<D>(J.lo, J.hi, Tp, e, sh, sw, fr);
     if (sn < 0)
         return false;
     float thr;
     int j1;
     const int m = leaf_filter<D>(J.lo, J.hi, sn, e, sh, thr, j1);
     const LeafPts<D> P = load_pts<D>(A, J);
-    leaf_listed<D>(A, J, m, j1, thr, sn, e, sh, P, st);
+    leaf_listed<D>(A, J, m, j1, thr, sn, e, sh, P, Tp, st);
     return true;
 }
 
@@ -840,6 +845,7 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t
 {
     const int lane = lane_id();
     const float e = err_bound(A.cmax_bits);
+    const TreeArgs *Tp = A.trees + A.group_cloud[g];
     const int64_t l0 = A.group_leaf[g];
     const int nl = A.group_leaf[g + 1] - (int)l0; // 1..GROUP_LEAVES
     LeafRegs r;
@@ -859,7 +865,7 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t
     if (lane < nl && r.own >= 0) {
         float cc[3];
         f4_to(A.c32[r.own], cc);
-        keep = inter_keep(A.cb_lo[r.own], box_maxd<D>(r.lo, r.hi, cc), e);
+        keep = inter_keep(A.cb_s[r.own], box_maxd<D>(r.lo, r.hi, cc), e);
     }
     const uint64_t kept = __ballot(keep);
     uint64_t todo = __ballot(lane < nl) & ~kept;
@@ -877,13 +883,13 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t
         ulo[i] = wave_min_f32(mine ? r.lo[i] : INFINITY);
         uhi[i] = -wave_min_f32(mine ? -r.hi[i] : INFINITY);
     }
-    const int sn = wave_search<D>(ulo, uhi, A, e, sh, A.sw_main, A.fr_main);
+    const int sn = wave_search<D>(ulo, uhi, Tp, e, sh, A.sw_main, A.fr_main);
     if (sn < 0) {
         // the list does not fit: search leaf by leaf
         st[ST_GROUP_OVF] += 1;
         for (uint64_t q = todo; q; q &= q - 1) {
             const LeafJob J = job_of<D>(r, __ffsll((unsigned long long)q) - 1, l0);
-            if (!leaf_searched<D>(A, J, e, sh, A.sw_main, A.fr_main, st))
+            if (!leaf_searched<D>(A, J, e, sh, A.sw_main, A.fr_main, Tp, st))
                 defer_leaf(A, J.l, st);
         }
         return;
@@ -929,7 +935,7 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t
             defer_leaf(A, J.l, st);
             continue;
         }
-        leaf_listed<D>(A, J, m, rl_i(r_j, t), rl_f(r_thr, t), sn, e, sh, P, st);
+        leaf_listed<D>(A, J, m, rl_i(r_j, t), rl_f(r_thr, t), sn, e, sh, P, Tp, st);
     }
 }
 
@@ -978,8 +984,9 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
     const int cnt = uniform_int(*A.heavy_cnt);
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         const LeafJob J = job_load<D>(A, A.heavy[i]);
+        const TreeArgs *Tp = A.trees + A.leaf_cloud[J.l];
         if (w == 0) {
-            const int sn = wave_search<D>(J.lo, J.hi, A, e, hs.ws, A.sw_heavy, A.fr_heavy);
+            const int sn = wave_search<D>(J.lo, J.hi, Tp, e, hs.ws, A.sw_heavy, A.fr_heavy);
             if (lane == 0)
                 hs.sn = sn;
         }
@@ -1008,10 +1015,10 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
             }
         } else if (w == 0) {
             if (sn < 0) {
-                leaf_all<D>(A, J, e, st);
+                leaf_all<D>(A, J, e, Tp, st);
             } else {
                 const LeafPts<D> P = load_pts<D>(A, J);
-                leaf_listed<D>(A, J, m, j1, thr, sn, e, hs.ws, P, st);
+                leaf_listed<D>(A, J, m, j1, thr, sn, e, hs.ws, P, Tp, st);
             }
         }
         __syncthreads(); // the workgroup's LDS is free for the next leaf
@@ -1086,7 +1093,7 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_brute32(AssignArgs A)
         double xd[D];
         for (int i = 0; i < D; ++i)
             xd[i] = (double)x[i];
-        best = brute64_all<D>(xd, A);
+        best = brute64_all<D>(xd, A, 0, A.k);
     }
     st[ST_RECHECK] += re ? 1 : 0;
     st[ST_EVALS] += valid ? A.k : 0;
@@ -1209,7 +1216,7 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in)
     A.c_in = c_in;
     A.c32 = ctx->c32;
     A.cmax_bits = (const unsigned *)ctx->cerr;
-    A.cb_lo = ctx->cb_lo;
+    A.cb_s = (const float *)ctx->cb_s;
     A.leaf_start = ctx->leaf_start;
     A.L = ctx->L;
     A.leaf_box = (const float4 *)ctx->leaf_box;
@@ -1220,7 +1227,9 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in)
     A.group_leaf = ctx->group_leaf;
     A.group_box = ctx->group_box;
     A.ngroups = ctx->ngroups;
-    A.T = ctx->tree;
+    A.trees = ctx->trees;
+    A.group_cloud = ctx->group_cloud;
+    A.leaf_cloud = ctx->leaf_cloud;
     A.S = ctx->S;
     A.fix64 = ctx->fix64;
     A.acc = ctx->acc;

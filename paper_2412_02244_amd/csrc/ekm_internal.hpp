@@ -17,14 +17,15 @@ namespace ekm {
 
 constexpr int WAVE = 64;
 constexpr int MAX_LEAF = 64;     // a leaf fits one wave
-constexpr int GROUP_LEAVES = 8;  // consecutive leaves sharing one centroid-tree descent (one wave)
-constexpr int HEAVY_M = 24;      // leaves with more candidates get a wave of their own
+constexpr int GROUP_LEAVES = 8;  // most consecutive leaves sharing one centroid-tree descent (one wave)
+// Leaves with more candidates than this go to the per-leaf pass.  At the
+// main pass's list capacity, only leaves whose candidate list does not fit
+// are deferred (measured: deferring crowded leaves cost more in the extra
+// pass than it saved in the main one); the small-list test mode lowers it.
+constexpr int HEAVY_M = 256;
 // Workgroups of the per-leaf pass (one per CU): workgroup b takes the
 // deferred leaves b, b + HEAVY_BLOCKS, ... of the step's list.
-constexpr int HEAVY_BLOCKS = 256;
-// Group cells: the largest Morton cells with at most this many points (a
-// multiple of the leaf size, so cells are unions of whole leaves).
-inline constexpr int group_cell_points(int f) { return 8 * f; }
+constexpr int HEAVY_BLOCKS = 64;
 constexpr int TREE_BUCKET = 8;   // centroids per centroid-tree leaf bucket
 constexpr int TREE_MAX_LEVELS = 8;
 constexpr int TREE_START_MAX = 512; // nodes a descent evaluates at its first level
@@ -57,7 +58,8 @@ enum CtlSlot {
     CTL_STABLE = 4,    // the current run stops when the assignment is stable
     CTL_N = 8,
 };
-constexpr int RUN_CHUNK = 8; // steps per launch group (graph) of kmeans_run
+constexpr int RUN_CHUNK = 8;  // steps per launch group (graph) of kmeans_run
+constexpr int RUN_AHEAD = 3;  // launch groups kmeans_run keeps queued while it waits for an earlier one
 
 // Common cluster of a leaf's points (leaf_own): a centroid id when every
 // point of the leaf is assigned to it, else one of these.
@@ -159,12 +161,14 @@ __device__ inline float prune_threshold(float U, float e)
 // where every other centroid is at exact distance >= cb from c_j, is
 // strictly nearer to c_j when 2 r < cb (triangle inequality).  s: an FP32
 // squared distance (or box max-distance) bounding r through dist_hi;
-// cb_lo: a lower bound on cb.  The factor 1 + 2^-14 keeps the gap far above
-// the FP32 rounding of the test and the FP64 rounding of the canonical
-// distances, so the kept centroid is also the strict FP64 argmin.
-__device__ inline bool inter_keep(float cb_lo, float s, float e)
+// cb_s: the smallest FP32 squared distance from fl32(c_j) to another fl32
+// centroid, so dist_lo(cb_s, 2e) <= cb (each centroid is within e of its
+// fl32 copy).  The factor 1 + 2^-14 keeps the gap far above the FP32
+// rounding of the test and the FP64 rounding of the canonical distances,
+// so the kept centroid is also the strict FP64 argmin.
+__device__ inline bool inter_keep(float cb_s, float s, float e)
 {
-    return cb_lo > 2.0f * dist_hi(s, e) * (1.0f + 0x1p-14f);
+    return dist_lo(cb_s, 2.0f * e) > 2.0f * dist_hi(s, e) * (1.0f + 0x1p-14f);
 }
 
 template <int D>
@@ -494,13 +498,30 @@ __device__ inline void wave_accumulate(bool valid, int a, const int64_t (&hi)[D]
     }
 }
 
-// Implicit 8-ary centroid tree (see tree.hip).
+// Cloud of point (or sorted position) i: the b with off[b] <= i < off[b + 1]
+// (every cloud is non-empty).
+__device__ inline int cloud_of(const int64_t *off, int B, int64_t i)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Implicit 8-ary centroid tree of one cloud (see tree.hip).
 struct TreeArgs {
-    float4 *cs;               // [k] fl32 centroids in tree order, w = centroid id bits
+    float4 *cs;               // [k] fl32 centroids in tree order, w = global centroid id bits
     float4 *node_lo, *node_hi; // [nnodes] level 0 (buckets) first
     int nlev;                 // levels, the last one is the root
     int start;                // lowest level with at most TREE_START_MAX nodes
     int64_t nnodes;
+    int64_t k;                // centroids of the cloud
+    int64_t c0;               // global id of its first centroid
     int64_t lev_size[TREE_MAX_LEVELS];
     int64_t lev_off[TREE_MAX_LEVELS];
 };
@@ -522,6 +543,22 @@ struct km_ctx {
     int64_t n = 0, k = 0;
     int d = 2;
     int f = 64;          // maximum leaf size
+    int G = ekm::GROUP_LEAVES; // leaves per group (sharing one candidate list)
+    // clouds: a context holds B independent point sets, cloud b owning points
+    // [pt_off[b], pt_off[b+1]) and centroids [c_off[b], c_off[b+1]) of the
+    // concatenated arrays; its points keep to their own centroids.  Ids are
+    // global inside the context and cloud-local in assign_out.
+    int B = 1;
+    std::vector<int64_t> h_pt_off, h_c_off; // [B+1] on the host
+    int64_t *pt_off = nullptr, *c_off = nullptr; // [B+1] on the device
+    ekm::TreeArgs *trees = nullptr;  // [B] device copies of each cloud's tree arguments
+    std::vector<ekm::TreeArgs> h_trees;
+    ekm::Grid *grids = nullptr;      // [B] Morton grid of each cloud (its bounding box)
+    std::vector<ekm::Grid> h_grids;
+    int32_t *leaf_cloud = nullptr;   // [L]
+    int32_t *group_cloud = nullptr;  // [ngroups]
+    int64_t ncb_chunks = 0;          // inter-bound pair scan: runs of up to 64 centroids of one cloud
+    int32_t *cb_chunk_cloud = nullptr, *cb_chunk_first = nullptr;
     int tile = 1024;     // brute-path LDS tile (centroids)
     int S = 0;           // fixed-point scale exponent
     int fix64 = 0;       // every point's fixed-point coordinate fits FIX64_BITS bits
@@ -543,8 +580,10 @@ struct km_ctx {
     int32_t *cval = nullptr, *cval2 = nullptr;
     ekm::TreeArgs tree{};
     float *cerr = nullptr;        // [1] bits of an FP32 upper bound on max_j ||c_j||
-    // inter bound (Eq. (3)): cb_lo[j] <= min_{i != j} ||c_i - c_j|| <= cb_hi[j] (exact distances)
-    float *cb_lo = nullptr, *cb_hi = nullptr; // [k]
+    // inter bound (Eq. (3)): cb_s[j] = bits of the smallest FP32 squared distance from fl32(c_j)
+    // to another fl32 centroid; cb_hi[j] >= min_{i != j} ||c_i - c_j|| (large-k path, Eq. (9))
+    unsigned *cb_s = nullptr;     // [k]
+    float *cb_hi = nullptr;       // [k]
     double *c_prev = nullptr;     // [k][d] centroids of the previous step (drift, Eq. (9))
     unsigned *drift_max = nullptr; // [1] bits of max_j drift (large-k path)
     float *drift = nullptr;       // [k] drift of each centroid (large-k path)
@@ -569,7 +608,8 @@ struct km_ctx {
     ekm::Scratch mem;
     int steps_done = 0;
     int32_t *ctl = nullptr;       // [CTL_N] device-side loop control
-    int32_t *host_ctl = nullptr;  // pinned [CTL_N]
+    int32_t *host_ctl = nullptr;  // pinned [(RUN_AHEAD + 1) * CTL_N]: ctl copies taken after launch groups
+    hipEvent_t chunk_ev[ekm::RUN_AHEAD] = {}; // completion of those copies
     int64_t *stat_hist = nullptr; // [hist_cap][NSTAT + 1] per-step statistics of a run
     int64_t hist_cap = 0;
     // kmeans_run's captured chunk of RUN_CHUNK steps (one per centroid array)
@@ -614,6 +654,8 @@ km_status build_leaves(km_ctx *ctx, const void *points);
 
 // tree.hip
 km_status build_centroid_tree(km_ctx *ctx, const double *c_in);
+bool small_trees(const km_ctx *ctx);
+constexpr int TREE_SMALL_K = 4096; // largest cloud whose tree one workgroup builds in LDS
 hipError_t tree_setup();
 void tree_layout(int64_t k, TreeArgs &T);
 

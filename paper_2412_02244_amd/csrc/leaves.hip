@@ -10,8 +10,15 @@
 // ball pivot and radius) and the exact fixed-point sum of its points, so a
 // leaf that falls wholly into one cluster updates that cluster's sum without
 // reading its points (the paper's node-level sum-vector update).
+//
+// A context may hold several independent clouds (concatenated, cloud b owning
+// points [pt_off[b], pt_off[b+1])): each gets its own Morton grid over its
+// own bounding box, the sort orders points by (cloud, Morton key), and no
+// leaf or group spans two clouds.
 #include <math.h>
 #include <string.h>
+
+#include <algorithm>
 
 #include "ekm_internal.hpp"
 
@@ -40,16 +47,23 @@ __host__ inline float float_of_ord(int32_t o)
     return f;
 }
 
+// Input scan, workgroup (b, y) over points of cloud b: the cloud's box goes
+// to out[b], the non-finite flag and the exponent window (over all clouds)
+// to out[B].
 template <class T, int D>
-__global__ void __launch_bounds__(256) k_scan_points(const T *x, int64_t n, ScanOut *out)
+__global__ void __launch_bounds__(256) k_scan_points(const T *x, const int64_t *pt_off, int B, ScanOut *outs)
 {
+    const int b = blockIdx.x;
+    const int64_t p0 = pt_off[b], p1 = pt_off[b + 1];
+    ScanOut *out = outs + b;
+    ScanOut *glob = outs + B;
     float lo[D], hi[D];
     for (int i = 0; i < D; ++i) {
         lo[i] = INFINITY;
         hi[i] = -INFINITY;
     }
     int nonfin = 0, nelsb = -100000, emsb = -100000, anynz = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t p = p0 + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; p < p1; p += (int64_t)gridDim.y * blockDim.x) {
         for (int i = 0; i < D; ++i) {
             T v = x[p * D + i];
             if (!isfinite(v)) {
@@ -90,17 +104,19 @@ __global__ void __launch_bounds__(256) k_scan_points(const T *x, int64_t n, Scan
         atomicMax(&out->hi[i], ord_of(hi[i]));
     }
     if (nonfin)
-        atomicOr(&out->nonfinite, 1);
+        atomicOr(&glob->nonfinite, 1);
     if (anynz) {
-        atomicMax(&out->neg_elsb, nelsb);
-        atomicMax(&out->emsb, emsb);
-        atomicOr(&out->any_nonzero, 1);
+        atomicMax(&glob->neg_elsb, nelsb);
+        atomicMax(&glob->emsb, emsb);
+        atomicOr(&glob->any_nonzero, 1);
     }
 }
 
 // ------------------------------------------------------------ keys, gather
+// Morton key of every point on its cloud's grid (vals = the point index).
 template <class T, int D>
-__global__ void __launch_bounds__(256) k_point_keys(const T *x, int64_t n, Grid g, uint32_t *keys, int32_t *vals)
+__global__ void __launch_bounds__(256) k_point_keys(const T *x, int64_t n, const int64_t *pt_off, int B,
+                                                    const Grid *grids, uint32_t *keys, int32_t *vals)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n)
@@ -108,8 +124,34 @@ __global__ void __launch_bounds__(256) k_point_keys(const T *x, int64_t n, Grid 
     float q[D];
     for (int i = 0; i < D; ++i)
         q[i] = (float)x[p * D + i];
-    keys[p] = morton_key<D>(q, g);
+    keys[p] = morton_key<D>(q, grids[B == 1 ? 0 : cloud_of(pt_off, B, p)]);
     vals[p] = (int32_t)p;
+}
+
+// Cloud of every point, in the current order perm (the key of the stable
+// sort by cloud that follows the sort by Morton key).
+__global__ void __launch_bounds__(256) k_cloud_keys(const int32_t *perm, int64_t n, const int64_t *pt_off, int B,
+                                                    uint32_t *keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        keys[i] = (uint32_t)cloud_of(pt_off, B, perm[i]);
+}
+
+// Morton keys in the final order (position i holds point perm[i], of the
+// cloud that owns position i).
+template <class T, int D>
+__global__ void __launch_bounds__(256) k_keys_at(const T *x, const int32_t *perm, int64_t n, const int64_t *pt_off,
+                                                 int B, const Grid *grids, uint32_t *keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int64_t p = perm[i];
+    float q[D];
+    for (int d = 0; d < D; ++d)
+        q[d] = (float)x[p * D + d];
+    keys[i] = morton_key<D>(q, grids[cloud_of(pt_off, B, i)]);
 }
 
 template <class T, int D>
@@ -128,21 +170,27 @@ __global__ void __launch_bounds__(256) k_gather(const T *x, const int32_t *perm,
 // i-1 and i holds more than f points: then i-1 and i lie in different
 // children of that cell, and their leaves (the largest cells with <= f
 // points) differ.  Equal keys beyond f points are cut every f points.
+//
+// A cloud's first position always starts a leaf, and every search below
+// stays inside the cloud of position i ([c_lo, c_hi)).
 template <int D>
-__global__ void __launch_bounds__(256) k_leaf_flags(const uint32_t *keys, int64_t n, int f, uint32_t *flag)
+__global__ void __launch_bounds__(256) k_leaf_flags(const uint32_t *keys, int64_t n, int f, uint32_t *flag,
+                                                    const int64_t *pt_off, int B)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    if (i == 0) {
-        flag[0] = 1;
+    const int cl = B == 1 ? 0 : cloud_of(pt_off, B, i);
+    const int64_t c_lo = pt_off[cl], c_hi = pt_off[cl + 1];
+    if (i == c_lo) {
+        flag[i] = 1;
         return;
     }
     const int KB = key_bits(D);
     uint32_t a = keys[i - 1], b = keys[i];
     uint32_t out;
     if (a == b) {
-        int64_t lo = 0, hi = i; // first index with key == b
+        int64_t lo = c_lo, hi = i; // first index with key == b
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
             if (keys[mid] < b)
@@ -152,7 +200,7 @@ __global__ void __launch_bounds__(256) k_leaf_flags(const uint32_t *keys, int64_
         }
         int64_t rs = lo;
         lo = i;
-        hi = n; // first index with key > b
+        hi = c_hi; // first index with key > b
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
             if (keys[mid] <= b)
@@ -168,7 +216,7 @@ __global__ void __launch_bounds__(256) k_leaf_flags(const uint32_t *keys, int64_
         const uint32_t keymask = KB == 32 ? ~0u : ((1u << (KB & 31)) - 1u);
         uint32_t mask = P == 0 ? 0u : ((~0u) << (KB - P)) & keymask;
         uint32_t cell = b & mask;
-        int64_t wlo = i - 1 - f < 0 ? 0 : i - 1 - f;
+        int64_t wlo = i - 1 - f < c_lo ? c_lo : i - 1 - f;
         int64_t lo = wlo, hi = i - 1; // first index in [wlo, i-1] inside the cell
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
@@ -178,7 +226,7 @@ __global__ void __launch_bounds__(256) k_leaf_flags(const uint32_t *keys, int64_
                 hi = mid;
         }
         int64_t s = lo;
-        int64_t whi = i + f + 1 > n ? n : i + f + 1;
+        int64_t whi = i + f + 1 > c_hi ? c_hi : i + f + 1;
         lo = i;
         hi = whi; // first index in [i, whi) past the cell
         while (lo < hi) {
@@ -238,9 +286,9 @@ __global__ void __launch_bounds__(256) k_leaf_info(const float *xs, int64_t n, c
 
 // ------------------------------------------------------------ wave groups
 // Leaves are grouped for the centroid-tree descent: a group is a run of at
-// most GROUP_LEAVES consecutive leaves inside one group cell, the largest
-// Morton cell holding at most GROUP_CELL_POINTS(f) points (the leaf rule at
-// a coarser threshold).  Group boxes then stay inside one compact cell; runs
+// most G (<= GROUP_LEAVES) consecutive leaves inside one group cell, the
+// largest Morton cell holding at most G * f points (the leaf rule at a
+// coarser threshold).  Group boxes then stay inside one compact cell; runs
 // of consecutive leaves across a Morton jump would give boxes spanning
 // distant regions.  Every group-cell cut is a leaf cut (the threshold is a
 // multiple of f), so cells are unions of whole leaves.
@@ -263,16 +311,32 @@ __global__ void __launch_bounds__(256) k_cell_first(const uint32_t *cs, const ui
         cell_first[cscan[l]] = (int32_t)l;
 }
 
-// ws[l] = 1 iff leaf l starts a group: its rank in its cell is a multiple of GROUP_LEAVES.
+// ws[l] = 1 iff leaf l starts a group: its rank in its cell is a multiple of G.
 __global__ void __launch_bounds__(256) k_group_starts(const uint32_t *cs, const uint32_t *cscan,
-                                                      const int32_t *cell_first, int64_t L, uint32_t *ws)
+                                                      const int32_t *cell_first, int64_t L, int G, uint32_t *ws)
 {
     int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L)
         return;
     const int64_t cell = (int64_t)cscan[l] + cs[l] - 1;
     const int64_t rank = l - cell_first[cell];
-    ws[l] = (rank % GROUP_LEAVES) == 0 ? 1u : 0u;
+    ws[l] = (rank % G) == 0 ? 1u : 0u;
+}
+
+// Cloud of every leaf (from its first point) and of every group (from its first leaf).
+__global__ void __launch_bounds__(256) k_leaf_clouds(const int32_t *leaf_start, int64_t L, const int64_t *pt_off,
+                                                     int B, int32_t *leaf_cloud)
+{
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < L)
+        leaf_cloud[l] = B == 1 ? 0 : cloud_of(pt_off, B, leaf_start[l]);
+}
+__global__ void __launch_bounds__(256) k_group_clouds(const int32_t *group_leaf, int64_t ngroups,
+                                                      const int32_t *leaf_cloud, int32_t *group_cloud)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ngroups)
+        group_cloud[g] = leaf_cloud[group_leaf[g]];
 }
 
 __global__ void __launch_bounds__(256) k_group_first(const uint32_t *ws, const uint32_t *gscan, int64_t L,
@@ -314,54 +378,77 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
 {
     hipStream_t st = ctx->stream;
     const int64_t n = ctx->n;
-    // 1. input scan
-    ScanOut h0;
-    for (int i = 0; i < 3; ++i) {
-        h0.lo[i] = 0x7fffffff;
-        h0.hi[i] = (int32_t)0x80000000;
+    const int B = ctx->B;
+    const int64_t *pt_off = ctx->pt_off;
+    // 1. input scan: each cloud's box, the non-finite flag and the exact-sum
+    //    window over all clouds (slot B)
+    std::vector<ScanOut> h0(B + 1);
+    for (auto &o : h0) {
+        for (int i = 0; i < 3; ++i) {
+            o.lo[i] = 0x7fffffff;
+            o.hi[i] = (int32_t)0x80000000;
+        }
+        o.nonfinite = 0;
+        o.neg_elsb = -100000;
+        o.emsb = -100000;
+        o.any_nonzero = 0;
     }
-    h0.nonfinite = 0;
-    h0.neg_elsb = -100000;
-    h0.emsb = -100000;
-    h0.any_nonzero = 0;
-    ScanOut *d0 = ctx_alloc<ScanOut>(ctx, 1);
+    ScanOut *d0 = ctx_alloc<ScanOut>(ctx, B + 1);
     if (!d0) {
         set_error("kmeans_init: device allocation failed");
         return KM_ERR_OOM;
     }
-    if (!hip_ok(hipMemcpyAsync(d0, &h0, sizeof(h0), hipMemcpyHostToDevice, st), "hipMemcpyAsync"))
+    if (!hip_ok(hipMemcpyAsync(d0, h0.data(), (B + 1) * sizeof(ScanOut), hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync"))
         return KM_ERR_HIP;
-    unsigned g = nblocks(n, 256);
-    if (g > 1024)
-        g = 1024;
-    hipLaunchKernelGGL((k_scan_points<T, D>), dim3(g), dim3(256), 0, st, x, n, d0);
-    if (!hip_ok(hipMemcpyAsync(&h0, d0, sizeof(h0), hipMemcpyDeviceToHost, st), "hipMemcpyAsync") ||
+    int64_t nmax = 0;
+    for (int b = 0; b < B; ++b)
+        nmax = std::max(nmax, ctx->h_pt_off[b + 1] - ctx->h_pt_off[b]);
+    unsigned gy = nblocks(nmax, 256 * 4);
+    gy = gy < 1 ? 1 : (gy > (B == 1 ? 1024u : 64u) ? (B == 1 ? 1024u : 64u) : gy);
+    hipLaunchKernelGGL((k_scan_points<T, D>), dim3((unsigned)B, gy), dim3(256), 0, st, x, pt_off, B, d0);
+    if (!hip_ok(hipMemcpyAsync(h0.data(), d0, (B + 1) * sizeof(ScanOut), hipMemcpyDeviceToHost, st),
+                "hipMemcpyAsync") ||
         !hip_ok(hipStreamSynchronize(st), "hipStreamSynchronize"))
         return KM_ERR_HIP;
-    if (h0.nonfinite) {
+    const ScanOut &hg = h0[B];
+    if (hg.nonfinite) {
         set_error("kmeans_init: points contain NaN or Inf");
         return KM_ERR_INVALID;
     }
     // exact-sum window
-    int S = h0.any_nonzero ? h0.neg_elsb : 0;
+    int S = hg.any_nonzero ? hg.neg_elsb : 0;
     int logn = 0;
     while (((int64_t)1 << logn) < n)
         ++logn;
-    int W = h0.any_nonzero ? h0.emsb + 1 + S + logn : 0;
+    int W = hg.any_nonzero ? hg.emsb + 1 + S + logn : 0;
     if (W > MAX_FIX_BITS) {
         set_error("kmeans_init: coordinates span " + std::to_string(W) +
                   " bits of fixed point; exact centroid sums support at most " + std::to_string(MAX_FIX_BITS));
         return KM_ERR_NOT_EXACT;
     }
     ctx->S = S;
-    ctx->fix64 = (h0.any_nonzero ? h0.emsb + 1 + S : 0) <= FIX64_BITS ? 1 : 0;
-    for (int i = 0; i < D; ++i) {
-        float lo = float_of_ord(h0.lo[i]), hi = float_of_ord(h0.hi[i]);
-        ctx->grid.lo[i] = lo;
-        float ext = hi - lo;
-        ctx->grid.scale[i] = ext > 0.0f ? (float)(1u << morton_bits(D)) / ext : 0.0f;
+    ctx->fix64 = (hg.any_nonzero ? hg.emsb + 1 + S : 0) <= FIX64_BITS ? 1 : 0;
+    // each cloud's Morton grid over its own box
+    ctx->h_grids.assign(B, Grid{});
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < D; ++i) {
+            float lo = float_of_ord(h0[b].lo[i]), hi = float_of_ord(h0[b].hi[i]);
+            ctx->h_grids[b].lo[i] = lo;
+            float ext = hi - lo;
+            ctx->h_grids[b].scale[i] = ext > 0.0f ? (float)(1u << morton_bits(D)) / ext : 0.0f;
+        }
+    ctx->grid = ctx->h_grids[0];
+    ctx->grids = ctx_alloc<Grid>(ctx, B);
+    if (!ctx->grids) {
+        set_error("kmeans_init: device allocation failed");
+        return KM_ERR_OOM;
     }
-    // 2. Morton sort
+    if (!hip_ok(hipMemcpyAsync(ctx->grids, ctx->h_grids.data(), B * sizeof(Grid), hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync"))
+        return KM_ERR_HIP;
+    // 2. sort by Morton key, then (several clouds) stably by cloud: the
+    //    points are ordered by (cloud, Morton key)
     uint32_t *keys = ctx_alloc<uint32_t>(ctx, n), *keys2 = ctx_alloc<uint32_t>(ctx, n);
     int32_t *vals2 = ctx_alloc<int32_t>(ctx, n);
     ctx->perm = ctx_alloc<int32_t>(ctx, n);
@@ -372,18 +459,35 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         set_error("kmeans_init: device allocation failed");
         return KM_ERR_OOM;
     }
-    hipLaunchKernelGGL((k_point_keys<T, D>), dim3(nblocks(n, 256)), dim3(256), 0, st, x, n, ctx->grid, keys,
-                       ctx->perm);
+    hipLaunchKernelGGL((k_point_keys<T, D>), dim3(nblocks(n, 256)), dim3(256), 0, st, x, n, pt_off, B,
+                       (const Grid *)ctx->grids, keys, ctx->perm);
     bool in_tmp = false;
     if (!hip_ok(radix_sort_u32(keys, ctx->perm, keys2, vals2, n, key_bits(D), hist, scan_tmp, st, &in_tmp),
                 "radix sort"))
         return KM_ERR_HIP;
     uint32_t *skeys = in_tmp ? keys2 : keys;    // sorted keys
     uint32_t *flag = in_tmp ? keys : keys2;     // free buffer
-    uint32_t *scan = (uint32_t *)vals2;         // free once perm is in place
     if (in_tmp &&
         !hip_ok(hipMemcpyAsync(ctx->perm, vals2, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "copy"))
         return KM_ERR_HIP;
+    if (B > 1) {
+        int cbits = 0;
+        while ((1 << cbits) < B)
+            ++cbits;
+        hipLaunchKernelGGL(k_cloud_keys, dim3(nblocks(n, 256)), dim3(256), 0, st, ctx->perm, n, pt_off, B, skeys);
+        in_tmp = false;
+        if (!hip_ok(radix_sort_u32(skeys, ctx->perm, flag, vals2, n, cbits, hist, scan_tmp, st, &in_tmp),
+                    "radix sort by cloud"))
+            return KM_ERR_HIP;
+        if (in_tmp &&
+            !hip_ok(hipMemcpyAsync(ctx->perm, vals2, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "copy"))
+            return KM_ERR_HIP;
+        hipLaunchKernelGGL((k_keys_at<T, D>), dim3(nblocks(n, 256)), dim3(256), 0, st, x, ctx->perm, n, pt_off, B,
+                           (const Grid *)ctx->grids, keys);
+        skeys = keys;
+        flag = keys2;
+    }
+    uint32_t *scan = (uint32_t *)vals2;         // free once perm is in place
     // 3. gather to SoA
     T *xs = ctx_alloc<T>(ctx, (size_t)n * D);
     if (!xs) {
@@ -393,7 +497,7 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
     ctx->xs = xs;
     hipLaunchKernelGGL((k_gather<T, D>), dim3(nblocks(n, 256)), dim3(256), 0, st, x, ctx->perm, n, xs);
     // 4. leaves
-    hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n, ctx->f, flag);
+    hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n, ctx->f, flag, pt_off, B);
     if (!hip_ok(hipMemcpyAsync(scan, flag, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy") ||
         !hip_ok(exclusive_scan_u32(scan, n, scan_tmp, st), "scan"))
         return KM_ERR_HIP;
@@ -413,17 +517,20 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
     if (sizeof(T) == 4 && ctx->cfg.algo == KM_INDEXED) {
         ctx->leaf_box = (float *)ctx_alloc<float4>(ctx, 2 * L);
         ctx->leaf_sum = ctx_alloc<int64_t>(ctx, (size_t)L * D * 2);
-        if (!ctx->leaf_box || !ctx->leaf_sum) {
+        ctx->leaf_cloud = ctx_alloc<int32_t>(ctx, L);
+        if (!ctx->leaf_box || !ctx->leaf_sum || !ctx->leaf_cloud) {
             set_error("kmeans_init: device allocation failed");
             return KM_ERR_OOM;
         }
         hipLaunchKernelGGL((k_leaf_info<D>), dim3(nblocks(L * WAVE, 256)), dim3(256), 0, st, (const float *)xs, n,
                            ctx->leaf_start, L, S, (float4 *)ctx->leaf_box, ctx->leaf_sum);
+        hipLaunchKernelGGL(k_leaf_clouds, dim3(nblocks(L, 256)), dim3(256), 0, st, (const int32_t *)ctx->leaf_start,
+                           L, pt_off, B, ctx->leaf_cloud);
         // wave groups (flag and scan are free again; the leaf-level arrays
         // live in scan, which holds n >= 4L words once L <= n/4, else in a
-        // temporary)
-        hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n,
-                           group_cell_points(ctx->f), flag);
+        // temporary): group cells are the leaf rule at G times the leaf size
+        hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n, ctx->G * ctx->f,
+                           flag, pt_off, B);
         uint32_t *tmp = nullptr;
         uint32_t *lw = scan;
         if (4 * L > n) {
@@ -441,7 +548,7 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         if (ok) {
             hipLaunchKernelGGL(k_cell_first, dim3(nblocks(L, 256)), dim3(256), 0, st, cs, cscan, L, cell_first);
             hipLaunchKernelGGL(k_group_starts, dim3(nblocks(L, 256)), dim3(256), 0, st, cs, cscan,
-                               (const int32_t *)cell_first, L, ws);
+                               (const int32_t *)cell_first, L, ctx->G, ws);
             ok = hip_ok(hipMemcpyAsync(gscan, ws, L * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy") &&
                  hip_ok(exclusive_scan_u32(gscan, L, scan_tmp, st), "scan") &&
                  hip_ok(hipMemcpyAsync(&last[0], gscan + L - 1, 4, hipMemcpyDeviceToHost, st), "copy") &&
@@ -452,7 +559,8 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
             ctx->ngroups = (int64_t)last[0] + last[1];
             ctx->group_leaf = ctx_alloc<int32_t>(ctx, ctx->ngroups + 1);
             ctx->group_box = ctx_alloc<float4>(ctx, 2 * ctx->ngroups);
-            if (!ctx->group_leaf || !ctx->group_box) {
+            ctx->group_cloud = ctx_alloc<int32_t>(ctx, ctx->ngroups);
+            if (!ctx->group_leaf || !ctx->group_box || !ctx->group_cloud) {
                 if (tmp)
                     (void)hipFree(tmp);
                 set_error("kmeans_init: device allocation failed");
@@ -463,6 +571,9 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
             hipLaunchKernelGGL(k_group_boxes, dim3(nblocks(ctx->ngroups, 256)), dim3(256), 0, st,
                                (const float4 *)ctx->leaf_box, (const int32_t *)ctx->group_leaf, ctx->ngroups,
                                ctx->group_box);
+            hipLaunchKernelGGL(k_group_clouds, dim3(nblocks(ctx->ngroups, 256)), dim3(256), 0, st,
+                               (const int32_t *)ctx->group_leaf, ctx->ngroups, (const int32_t *)ctx->leaf_cloud,
+                               ctx->group_cloud);
             ok = hip_ok(hipStreamSynchronize(st), "sync");
         }
         if (tmp)

@@ -111,12 +111,15 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, do
     }
 }
 
+// Caller order and cloud-local centroid ids (position i of the Morton order
+// belongs to the cloud whose point range holds i).
 __global__ void __launch_bounds__(256) k_scatter_assign(const int32_t *a, const int32_t *perm, int64_t n,
+                                                        const int64_t *pt_off, const int64_t *c_off, int B,
                                                         int32_t *out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
-        out[perm[i]] = a[i];
+        out[perm[i]] = B == 1 ? a[i] : a[i] - (int32_t)c_off[cloud_of(pt_off, B, i)];
 }
 
 int64_t assign_blocks(const km_ctx *ctx);
@@ -170,7 +173,8 @@ km_status set_ctl(km_ctx *ctx, int32_t max_iter, int32_t stable, int32_t reset_r
 km_status scatter_assignment(km_ctx *ctx, int32_t *assign_out)
 {
     hipLaunchKernelGGL(k_scatter_assign, dim3((unsigned)((ctx->n + 255) / 256)), dim3(256), 0, ctx->stream, ctx->a,
-                       ctx->perm, ctx->n, assign_out);
+                       ctx->perm, ctx->n, (const int64_t *)ctx->pt_off, (const int64_t *)ctx->c_off, ctx->B,
+                       assign_out);
     if (!hip_ok(hipGetLastError(), "scatter launch"))
         return KM_ERR_HIP;
     return KM_OK;

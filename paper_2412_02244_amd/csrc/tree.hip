@@ -16,7 +16,8 @@
 
 namespace ekm {
 
-constexpr int SMALL_K = 4096;
+constexpr int SMALL_K = TREE_SMALL_K;
+constexpr int TREE_RESORT = 8; // the small-k tree re-sorts its centroids every this many steps
 constexpr int TREE_THREADS = 1024;
 constexpr int TREE_WAVES = TREE_THREADS / WAVE;
 
@@ -165,17 +166,29 @@ __device__ inline float err_of(float cmax) { return cmax * 0x1p-24f * (1.0f + 0x
 
 // ------------------------------------------------------------------ small k
 // Everything in one workgroup, LDS-resident after one read of the centroids:
-// prep, stable LSD radix sort (8-bit digits) of the top 16 key bits, the
-// tree-ordered copy and every node box; global memory is only written.
+// prep, the tree order, the tree-ordered copy and every node box; global
+// memory is only written (and, between re-sorts, the previous order read).
+// The Morton sort (stable LSD radix sort, 8-bit digits, top 16 key bits)
+// runs on every TREE_RESORT-th step of a context; in between, the previous
+// step's order is kept and only the boxes are recomputed from the current
+// centroids.  Any grouping of the centroids gives exact boxes, so the order
+// only affects how tight the boxes are (centroids move little from step to
+// step), never which centroids are candidates.
+// One workgroup per cloud (blockIdx.x): its centroids are [T.c0, T.c0 + T.k)
+// of the concatenated arrays, with tree positions local to the cloud and
+// global ids in cs[].w.
 template <int D>
-__global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, int64_t k, Grid g, TreeArgs T,
-                                                             float4 *c32, unsigned *cmax_bits, double *c_prev,
-                                                             float *cb_lo, float *cb_hi, const int32_t *ctl)
+__global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all, const TreeArgs *trees,
+                                                             const Grid *grids, float4 *c32, unsigned *cmax_bits,
+                                                             unsigned *cb_s, const int32_t *ctl)
 {
     if (ctl[CTL_STOP])
         return; // the run is over (the whole workgroup returns)
-    const int have_prev = ctl[CTL_STEPS] > 0;
-    __shared__ float cmax_sh, dmax_sh;
+    const TreeArgs &T = trees[blockIdx.x];
+    const Grid g = grids[blockIdx.x];
+    const int64_t c0 = T.c0, k = T.k;
+    const double *c = c_all + c0 * D;
+    const int resort = uniform_int(ctl[CTL_STEPS] % TREE_RESORT == 0 ? 1 : 0);
     extern __shared__ unsigned char smem[];
     float4 *cq = (float4 *)smem;              // [SMALL_K] fl32 centroids, caller order
     uint32_t *key = (uint32_t *)(cq + SMALL_K); // [SMALL_K]
@@ -194,9 +207,11 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, in
         uint32_t kb;
         nb = fmaxf(nb, centroid_prep_one<D>(c, j, g, q4, kb));
         cq[j] = q4;
-        c32[j] = q4;
+        c32[c0 + j] = q4;
+        cb_s[c0 + j] = 0x7f800000u; // +inf: k_cb_pairs takes the minimum
         key[j] = kb >> shift;
-        id[j] = (uint32_t)j;
+        // the order to keep: tree position j held centroid T.cs[j].w (a global id)
+        id[j] = resort ? (uint32_t)j : (uint32_t)(__float_as_int(T.cs[j].w) - (int)c0);
     }
     nb = -wave_min_f32(-nb);
     if (lane == 0)
@@ -206,84 +221,86 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, in
         float m = 0.0f;
         for (int w = 0; w < TREE_WAVES; ++w)
             m = fmaxf(m, red[w]);
-        *cmax_bits = __float_as_uint(m);
-        cmax_sh = m;
+        atomicMax(cmax_bits, __float_as_uint(m)); // over all clouds (non-negative floats order like their bits)
     }
-    // two stable passes over 8-bit digits
-    for (int pass = 0; pass < 2; ++pass) {
-        const int sh = 8 * pass;
-        uint32_t *kin = pass ? key2 : key, *vin = pass ? id2 : id;
-        uint32_t *kout = pass ? key : key2, *vout = pass ? id : id2;
-        if (tid < 256)
-            base[tid] = 0;
-        __syncthreads();
-        for (int j = tid; j < kk; j += TREE_THREADS)
-            atomicAdd(&base[(kin[j] >> sh) & 0xffu], 1u);
-        __syncthreads();
-        // exclusive scan of the 256 digit counts: 4 waves scan 64 each
-        if (tid < 256) {
-            uint32_t v = base[tid], x = v;
-#pragma unroll
-            for (int o = 1; o < WAVE; o <<= 1) {
-                uint32_t y = __shfl_up(x, o);
-                if (lane >= o)
-                    x += y;
-            }
-            if (lane == WAVE - 1)
-                wcnt[wid] = x; // wave totals (wcnt is free here)
-            base[tid] = x - v;
-        }
-        __syncthreads();
-        if (tid < 256) {
-            uint32_t add = 0;
-            for (int w = 0; w < wid; ++w)
-                add += wcnt[w];
-            base[tid] += add;
-        }
-        __syncthreads();
-        for (int r0 = 0; r0 < kk; r0 += TREE_THREADS) {
+    if (resort) {
+        // two stable passes over 8-bit digits
+        for (int pass = 0; pass < 2; ++pass) {
+            const int sh = 8 * pass;
+            uint32_t *kin = pass ? key2 : key, *vin = pass ? id2 : id;
+            uint32_t *kout = pass ? key : key2, *vout = pass ? id : id2;
             if (tid < 256)
-                for (int w = 0; w < TREE_WAVES; ++w)
-                    wcnt[w * 256 + tid] = 0;
+                base[tid] = 0;
             __syncthreads();
-            int j = r0 + tid;
-            bool valid = j < kk;
-            uint32_t kv = valid ? kin[j] : 0u, vv = valid ? vin[j] : 0u;
-            uint32_t dig = (kv >> sh) & 0xffu;
-            uint64_t m = __ballot(valid);
+            for (int j = tid; j < kk; j += TREE_THREADS)
+                atomicAdd(&base[(kin[j] >> sh) & 0xffu], 1u);
+            __syncthreads();
+            // exclusive scan of the 256 digit counts: 4 waves scan 64 each
+            if (tid < 256) {
+                uint32_t v = base[tid], x = v;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                uint64_t bal = __ballot((dig >> b) & 1u);
-                m &= ((dig >> b) & 1u) ? bal : ~bal;
+                for (int o = 1; o < WAVE; o <<= 1) {
+                    uint32_t y = __shfl_up(x, o);
+                    if (lane >= o)
+                        x += y;
+                }
+                if (lane == WAVE - 1)
+                    wcnt[wid] = x; // wave totals (wcnt is free here)
+                base[tid] = x - v;
             }
-            int rank = __popcll(m & lanemask_lt());
-            if (valid && rank == 0)
-                wcnt[wid * 256 + dig] = (uint32_t)__popcll(m);
-            __syncthreads();
-            uint32_t pos = base[dig] + (uint32_t)rank;
-            for (int w = 0; w < wid; ++w)
-                pos += wcnt[w * 256 + dig];
             __syncthreads();
             if (tid < 256) {
                 uint32_t add = 0;
-                for (int w = 0; w < TREE_WAVES; ++w)
-                    add += wcnt[w * 256 + tid];
+                for (int w = 0; w < wid; ++w)
+                    add += wcnt[w];
                 base[tid] += add;
             }
-            if (valid) {
-                kout[pos] = kv;
-                vout[pos] = vv;
-            }
             __syncthreads();
+            for (int r0 = 0; r0 < kk; r0 += TREE_THREADS) {
+                if (tid < 256)
+                    for (int w = 0; w < TREE_WAVES; ++w)
+                        wcnt[w * 256 + tid] = 0;
+                __syncthreads();
+                int j = r0 + tid;
+                bool valid = j < kk;
+                uint32_t kv = valid ? kin[j] : 0u, vv = valid ? vin[j] : 0u;
+                uint32_t dig = (kv >> sh) & 0xffu;
+                uint64_t m = __ballot(valid);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    uint64_t bal = __ballot((dig >> b) & 1u);
+                    m &= ((dig >> b) & 1u) ? bal : ~bal;
+                }
+                int rank = __popcll(m & lanemask_lt());
+                if (valid && rank == 0)
+                    wcnt[wid * 256 + dig] = (uint32_t)__popcll(m);
+                __syncthreads();
+                uint32_t pos = base[dig] + (uint32_t)rank;
+                for (int w = 0; w < wid; ++w)
+                    pos += wcnt[w * 256 + dig];
+                __syncthreads();
+                if (tid < 256) {
+                    uint32_t add = 0;
+                    for (int w = 0; w < TREE_WAVES; ++w)
+                        add += wcnt[w * 256 + tid];
+                    base[tid] += add;
+                }
+                if (valid) {
+                    kout[pos] = kv;
+                    vout[pos] = vv;
+                }
+                __syncthreads();
+            }
         }
     }
+    __syncthreads();
     // sorted ids are back in `id`; node boxes go to LDS (over key2/id2,
     // free now: at most 2 * SMALL_K / TREE_BUCKET float4 pairs) and out
     float4 *nlo = (float4 *)key2, *nhi = nlo + T.nnodes;
     for (int t = tid; t < kk; t += TREE_THREADS) {
         int cid = (int)id[t];
         float4 p = cq[cid];
-        p.w = __int_as_float(cid);
+        p.w = __int_as_float((int)c0 + cid);
         T.cs[t] = p;
     }
     const int nb0 = (int)T.lev_size[0];
@@ -314,62 +331,49 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c, in
         }
         __syncthreads();
     }
-    // inter bound: drift since the previous step, then the nearest-neighbour
-    // search of every centroid over the LDS tree
-    __shared__ int64_t lev_size_sh[TREE_MAX_LEVELS], lev_off_sh[TREE_MAX_LEVELS];
-    if (tid < TREE_MAX_LEVELS) {
-        lev_size_sh[tid] = T.lev_size[tid];
-        lev_off_sh[tid] = T.lev_off[tid];
+}
+
+// Inter bound of Eq. (3) for k <= SMALL_K: for every centroid, the smallest
+// FP32 squared distance to another centroid (both fl32), by scanning all
+// pairs.  Workgroup (x, y): centroids 64x .. 64x + 63 (one per lane), each
+// of its four waves the others i = 4y + w, 4y + w + 4 CB_SLICES, ...; the
+// partial minima meet through an atomic minimum on the float bits
+// (non-negative floats order like their bit patterns).  cb_s must hold
+// +inf beforehand (the tree kernel writes it).  The keep tests turn cb_s
+// into a lower bound on the exact distance between the FP64 centroids.
+constexpr int CB_THREADS = 256;
+constexpr int CB_SLICES = 16;
+//   chunk x: the up-to-64 centroids starting at global id chunk_first[x] of
+//   cloud chunk_cloud[x]; only that cloud's centroids are scanned.
+template <int D>
+__global__ void __launch_bounds__(CB_THREADS) k_cb_pairs(const float4 *c32, const TreeArgs *trees,
+                                                         const int32_t *chunk_cloud, const int32_t *chunk_first,
+                                                         unsigned *cb_s, const int32_t *ctl)
+{
+    if (ctl[CTL_STOP])
+        return;
+    const int lane = lane_id();
+    const TreeArgs &T = trees[chunk_cloud[blockIdx.x]];
+    const int64_t c0 = T.c0, c1 = T.c0 + T.k;
+    const int64_t j = (int64_t)chunk_first[blockIdx.x] + lane;
+    const int64_t stride = (int64_t)CB_SLICES * (CB_THREADS / WAVE);
+    const int64_t k = c1;
+    float cj[3] = {0.0f, 0.0f, 0.0f};
+    if (j < k)
+        f4_to3(c32[j], cj);
+    float best[2] = {INFINITY, INFINITY};
+    int u = 0;
+    for (int64_t i = c0 + (int64_t)blockIdx.y * (CB_THREADS / WAVE) + threadIdx.x / WAVE; i < k;
+         i += stride, u ^= 1) {
+        float q[3];
+        f4_to3(c32[i], q); // the same address in every lane: one broadcast load
+        const float sv = sqdist32<D>(cj, q);
+        if (i != j)
+            best[u] = fminf(best[u], sv); // two chains: shorter dependences
     }
-    float dm = 0.0f;
-    if (have_prev)
-        for (int t = tid; t < kk; t += TREE_THREADS) {
-            const int j = (int)id[t];
-            dm = fmaxf(dm, drift_bound<D>(c + (int64_t)j * D, c_prev + (int64_t)j * D));
-        }
-    dm = -wave_min_f32(-dm);
-    if (lane == 0)
-        red[wid] = dm;
-    __syncthreads();
-    if (tid == 0) {
-        float m = 0.0f;
-        for (int w = 0; w < TREE_WAVES; ++w)
-            m = fmaxf(m, red[w]);
-        dmax_sh = m;
-    }
-    __syncthreads();
-    const float e = err_of(cmax_sh), dmax = dmax_sh;
-    auto cent = [&](int64_t q, float *o) {
-        const float4 p = cq[id[q]];
-        o[0] = p.x;
-        o[1] = p.y;
-        o[2] = p.z;
-    };
-    auto box = [&](int l, int64_t i, float *lo, float *hi) {
-        const int64_t o = lev_off_sh[l] + i;
-        lo[0] = nlo[o].x;
-        lo[1] = nlo[o].y;
-        lo[2] = nlo[o].z;
-        hi[0] = nhi[o].x;
-        hi[1] = nhi[o].y;
-        hi[2] = nhi[o].z;
-    };
-    for (int t = tid; t < kk; t += TREE_THREADS) {
-        const int j = (int)id[t];
-        float cj[3];
-        cent(t, cj);
-        const double *cjd = c + (int64_t)j * D;
-        double *cpj = c_prev + (int64_t)j * D;
-        const float dj = have_prev ? drift_bound<D>(cjd, cpj) : 0.0f;
-        const float s0 = nn_bound(have_prev != 0, have_prev ? cb_hi[j] : 0.0f, dj, dmax, e);
-        float sm = nn_search<D>(t, cj, s0, lev_size_sh, T.nlev, kk, cent, box);
-        if (!(sm < s0) && s0 < INFINITY) // nothing below the bound: search without it
-            sm = nn_search<D>(t, cj, INFINITY, lev_size_sh, T.nlev, kk, cent, box);
-        cb_lo[j] = dist_lo(sm, 2.0f * e);
-        cb_hi[j] = dist_hi(sm, 2.0f * e);
-        for (int i = 0; i < D; ++i)
-            cpj[i] = cjd[i];
-    }
+    const float m = fminf(best[0], best[1]);
+    if (j < k && m < INFINITY)
+        atomicMin(cb_s + j, __float_as_uint(m));
 }
 
 // ------------------------------------------------------------------ large k
@@ -415,7 +419,7 @@ __global__ void __launch_bounds__(256) k_centroid_prep(const double *c, int64_t 
 // nearest-neighbour search over the tree in global memory.
 template <int D>
 __global__ void __launch_bounds__(256) k_centroid_nn(TreeArgs T, int64_t k, const unsigned *cmax_bits,
-                                                     const float *drift, const unsigned *drift_max, float *cb_lo,
+                                                     const float *drift, const unsigned *drift_max, unsigned *cb_s,
                                                      float *cb_hi, const int32_t *ctl)
 {
     if (ctl[CTL_STOP])
@@ -449,8 +453,8 @@ __global__ void __launch_bounds__(256) k_centroid_nn(TreeArgs T, int64_t k, cons
     float sm = nn_search<D>(t, cj, s0, lev_size_sh, T.nlev, k, cent, box);
     if (!(sm < s0) && s0 < INFINITY)
         sm = nn_search<D>(t, cj, INFINITY, lev_size_sh, T.nlev, k, cent, box);
-    cb_lo[j] = dist_lo(sm, 2.0f * e);
-    cb_hi[j] = dist_hi(sm, 2.0f * e);
+    cb_s[j] = __float_as_uint(sm);
+    cb_hi[j] = dist_hi(sm, 2.0f * e); // the next step's search bound (Eq. (9))
 }
 
 __global__ void __launch_bounds__(256) k_tree_buckets(const float4 *c32, const int32_t *sorted_id, int64_t k,
@@ -494,19 +498,37 @@ static size_t small_tree_lds()
 static_assert(2 * (SMALL_K / TREE_BUCKET + SMALL_K / TREE_BUCKET / 7 + 8) * 16 <= SMALL_K * 8,
               "node boxes of the small tree fit in LDS");
 
+// Every cloud's tree is built by one workgroup (k of each cloud at most SMALL_K).
+bool small_trees(const km_ctx *ctx)
+{
+    for (int b = 0; b < ctx->B; ++b)
+        if (ctx->h_c_off[b + 1] - ctx->h_c_off[b] > SMALL_K)
+            return false;
+    return true;
+}
+
 km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
 {
     hipStream_t st = ctx->stream;
     const int64_t k = ctx->k;
     unsigned *cmax = (unsigned *)ctx->cerr;
     const int32_t *hp = ctx->ctl;
-    if (ctx->cfg.algo == KM_INDEXED && k <= SMALL_K) {
-        if (ctx->d == 2)
-            hipLaunchKernelGGL(k_tree_small<2>, dim3(1), dim3(TREE_THREADS), small_tree_lds(), st, c_in, k, ctx->grid,
-                               ctx->tree, ctx->c32, cmax, ctx->c_prev, ctx->cb_lo, ctx->cb_hi, hp);
-        else
-            hipLaunchKernelGGL(k_tree_small<3>, dim3(1), dim3(TREE_THREADS), small_tree_lds(), st, c_in, k, ctx->grid,
-                               ctx->tree, ctx->c32, cmax, ctx->c_prev, ctx->cb_lo, ctx->cb_hi, hp);
+    if (ctx->cfg.algo == KM_INDEXED && small_trees(ctx)) {
+        const dim3 gb((unsigned)ctx->ncb_chunks, CB_SLICES);
+        const unsigned nb = (unsigned)ctx->B;
+        if (ctx->d == 2) {
+            hipLaunchKernelGGL(k_tree_small<2>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(), st, c_in,
+                               (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s, hp);
+            hipLaunchKernelGGL(k_cb_pairs<2>, gb, dim3(CB_THREADS), 0, st, (const float4 *)ctx->c32,
+                               (const TreeArgs *)ctx->trees, (const int32_t *)ctx->cb_chunk_cloud,
+                               (const int32_t *)ctx->cb_chunk_first, ctx->cb_s, hp);
+        } else {
+            hipLaunchKernelGGL(k_tree_small<3>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(), st, c_in,
+                               (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s, hp);
+            hipLaunchKernelGGL(k_cb_pairs<3>, gb, dim3(CB_THREADS), 0, st, (const float4 *)ctx->c32,
+                               (const TreeArgs *)ctx->trees, (const int32_t *)ctx->cb_chunk_cloud,
+                               (const int32_t *)ctx->cb_chunk_first, ctx->cb_s, hp);
+        }
         return hip_ok(hipGetLastError(), "centroid tree launch") ? KM_OK : KM_ERR_HIP;
     }
     unsigned g = (unsigned)((k + 255) / 256);
@@ -534,10 +556,10 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
         hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.lev_size[l] + 255) / 256)), dim3(256), 0, st, T, l);
     if (ctx->d == 2)
         hipLaunchKernelGGL(k_centroid_nn<2>, dim3(g), dim3(256), 0, st, T, k, (const unsigned *)cmax,
-                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_lo, ctx->cb_hi, hp);
+                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_s, ctx->cb_hi, hp);
     else
         hipLaunchKernelGGL(k_centroid_nn<3>, dim3(g), dim3(256), 0, st, T, k, (const unsigned *)cmax,
-                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_lo, ctx->cb_hi, hp);
+                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_s, ctx->cb_hi, hp);
     return hip_ok(hipGetLastError(), "centroid tree launch") ? KM_OK : KM_ERR_HIP;
 }
 

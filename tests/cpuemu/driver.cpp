@@ -8,6 +8,12 @@
 //   driver run in.bin out.bin            (same input; one kmeans_run call
 //          with stop_when_stable = flags >> 16 & 1, max_iter = iters)
 //     out: int32 iterations, assignment (n int32), centroids (k x d FP64)
+//   driver batched in.bin out.bin        (B clouds in one context: after the
+//          header, int64 B, pt_offs (B + 1), c_offs (B + 1); k is c_offs[B])
+//     out: as kmeans, with cloud-local assignments
+//   driver runb in.bin out.bin           (same input; one kmeans_run_batched
+//          call with the header's leaf_size and cand_tile = flags >> 20)
+//     out: int32 f, int32 G, assignment (n int32), centroids (k x d FP64)
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -25,7 +31,7 @@ static void die(const char *what)
 int main(int argc, char **argv)
 {
     if (argc != 4) {
-        fprintf(stderr, "usage: driver kmeans|run in.bin out.bin\n");
+        fprintf(stderr, "usage: driver kmeans|run|batched|runb in.bin out.bin\n");
         return 2;
     }
     FILE *f = fopen(argv[2], "rb");
@@ -35,6 +41,18 @@ int main(int argc, char **argv)
     if (fread(h, 8, 8, f) != 8)
         return 2;
     const int64_t n = h[0], d = h[1], k = h[2], iters = h[3];
+    const bool batched = !strcmp(argv[1], "batched") || !strcmp(argv[1], "runb");
+    int64_t B = 1;
+    std::vector<int64_t> pt_offs, c_offs;
+    if (batched) {
+        if (fread(&B, 8, 1, f) != 1)
+            return 2;
+        pt_offs.resize(B + 1);
+        c_offs.resize(B + 1);
+        if (fread(pt_offs.data(), 8, B + 1, f) != (size_t)(B + 1) ||
+            fread(c_offs.data(), 8, B + 1, f) != (size_t)(B + 1))
+            return 2;
+    }
     const size_t es = h[7] == KM_F32 ? 4 : 8;
     std::vector<unsigned char> pts(n * d * es);
     std::vector<double> c(k * d);
@@ -48,12 +66,29 @@ int main(int argc, char **argv)
     cfg.algo = (int32_t)h[4];
     cfg.leaf_size = (int32_t)h[5];
     cfg.flags = (uint32_t)(h[6] & 0xffff);
+    std::vector<int32_t> a(n);
+    if (!strcmp(argv[1], "runb")) {
+        cfg.cand_tile = (int32_t)((h[6] >> 20) & 0xfff);
+        cfg.flags = 0;
+        int32_t tuned[2] = {0, 0};
+        if (kmeans_run_batched(pts.data(), pt_offs.data(), c.data(), c_offs.data(), a.data(), (int32_t)B, &cfg,
+                               (int32_t)iters, nullptr, tuned) != KM_OK)
+            die("kmeans_run_batched");
+        FILE *o = fopen(argv[3], "wb");
+        fwrite(tuned, 4, 2, o);
+        fwrite(a.data(), 4, n, o);
+        fwrite(c.data(), 8, c.size(), o);
+        fclose(o);
+        return 0;
+    }
     km_ctx *ctx = nullptr;
-    if (kmeans_init(&ctx, &cfg, pts.data(), n, k, nullptr) != KM_OK)
+    if (batched) {
+        if (kmeans_init_batched(&ctx, &cfg, pts.data(), pt_offs.data(), c_offs.data(), (int32_t)B, nullptr) != KM_OK)
+            die("kmeans_init_batched");
+    } else if (kmeans_init(&ctx, &cfg, pts.data(), n, k, nullptr) != KM_OK)
         die("kmeans_init");
     FILE *o = fopen(argv[3], "wb");
-    std::vector<int32_t> a(n);
-    if (!strcmp(argv[1], "kmeans")) {
+    if (!strcmp(argv[1], "kmeans") || batched) {
         std::vector<double> cn(k * d);
         for (int64_t t = 0; t < iters; ++t) {
             km_iter_stats st;

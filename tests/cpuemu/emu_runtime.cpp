@@ -395,6 +395,12 @@ hipError_t hipGetLastError()
 }
 hipError_t hipPeekAtLastError() { return g_last; }
 const char *hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "emulated error"; }
+hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int)
+{
+    strcpy(p->gcnArchName, "cpu-emulation");
+    return hipSuccess;
+}
+
 hipError_t hipGetDevice(int *d)
 {
     *d = 0;
@@ -405,6 +411,7 @@ hipError_t hipEventCreate(hipEvent_t *e)
     *e = malloc(8);
     return hipSuccess;
 }
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { return hipEventCreate(e); }
 hipError_t hipEventDestroy(hipEvent_t e)
 {
     free(e);

@@ -188,7 +188,13 @@ hipError_t hipGetLastError();
 hipError_t hipPeekAtLastError();
 const char *hipGetErrorString(hipError_t);
 hipError_t hipGetDevice(int *d);
+struct hipDeviceProp_t {
+    char gcnArchName[256];
+};
+hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int d);
 hipError_t hipEventCreate(hipEvent_t *e);
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned flags);
+enum { hipEventDefault = 0, hipEventDisableTiming = 2 };
 hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s = nullptr);
 hipError_t hipEventSynchronize(hipEvent_t e);

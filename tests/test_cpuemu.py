@@ -140,3 +140,80 @@ def test_emulated_long_trajectory_inter_bounds(driver, tmp_path):
     kept_pt = sum(int(st["inter_points"]) for _, _, st in got[1:])
     assert kept_leaf > 0 and kept_pt > 0, (kept_leaf, kept_pt)
     assert got[0][2]["inter_leaf_points"] == 0  # nothing is kept before the first assignment
+
+
+def _clouds(sizes, ks, seed):
+    """Concatenated clouds of the given sizes (a mix of 2-D workloads) with
+    their own initial centroids, and the offsets of both."""
+    xs, cs = [], []
+    for b, (n, k) in enumerate(zip(sizes, ks)):
+        gen = (geo_hotspots_2d, gaussian_mixture_2d)[b % 2]
+        x = gen(n, seed=seed + 2 * b).astype(np.float32)
+        xs.append(x)
+        cs.append(init_centroids(x, k, seed + 2 * b + 1))
+    po = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    co = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+    return xs, cs, po, co
+
+
+def _run_batched(driver, tmp_path, mode, xs, cs, po, co, iters, leaf_size=0, cand_tile=0, flags=0):
+    x = np.concatenate(xs)
+    c0 = np.concatenate(cs)
+    n, d = x.shape
+    k = c0.shape[0]
+    B = len(xs)
+    inp, out = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(inp, "wb") as f:
+        np.array([n, d, k, iters, KM_INDEXED, leaf_size, flags | cand_tile << 20, KM_F32], np.int64).tofile(f)
+        np.array([B], np.int64).tofile(f)
+        po.tofile(f)
+        co.tofile(f)
+        x.tofile(f)
+        np.ascontiguousarray(c0, np.float64).tofile(f)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    r = subprocess.run([driver, mode, str(inp), str(out)], capture_output=True, text=True, env=env, timeout=900)
+    assert r.returncode == 0, f"emulated run failed ({r.returncode}):\n{r.stderr[-4000:]}"
+    raw = open(out, "rb").read()
+    if mode == "runb":
+        fG = np.frombuffer(raw[:8], np.int32)
+        return (int(fG[0]), int(fG[1])), np.frombuffer(raw[8:8 + 4 * n], np.int32), \
+            np.frombuffer(raw[8 + 4 * n:], np.float64).reshape(k, d)
+    step = 4 * n + 8 * k * d + STATS.itemsize
+    res = []
+    for t in range(iters):
+        b = raw[t * step:(t + 1) * step]
+        res.append((np.frombuffer(b[:4 * n], np.int32), np.frombuffer(b[4 * n:4 * n + 8 * k * d],
+                                                                      np.float64).reshape(k, d)))
+    return res
+
+
+def test_emulated_batched_clouds(driver, tmp_path):
+    """Clouds of different sizes and centroid counts (one with k_b = n_b, one
+    with a single centroid) in one context: every cloud's step equals the
+    oracle run on that cloud alone, with cloud-local centroid ids."""
+    sizes, ks = [900, 40, 1300, 7, 600], [14, 40, 25, 1, 9]
+    xs, cs, po, co = _clouds(sizes, ks, 90)
+    got = _run_batched(driver, tmp_path, "batched", xs, cs, po, co, 4, flags=KM_FLAG_SSE)
+    for b in range(len(xs)):
+        ref = oracle.lloyd(xs[b], cs[b], max_iter=4)
+        for t, (a, c) in enumerate(got):
+            np.testing.assert_array_equal(a[po[b]:po[b + 1]], ref["a_hist"][t], err_msg=f"cloud {b} step {t + 1}")
+            np.testing.assert_array_equal(c[co[b]:co[b + 1]], ref["c_hist"][t], err_msg=f"cloud {b} step {t + 1}")
+
+
+def test_emulated_run_batched_autotune(driver, tmp_path):
+    """kmeans_run_batched with leaf size and list length left to the tuner
+    (it times its candidates on the clouds, then runs them all): the result
+    is the oracle's whatever it picked, and the pick is one of the candidates."""
+    sizes, ks = [700, 500, 800], [10, 6, 12]
+    xs, cs, po, co = _clouds(sizes, ks, 95)
+    (f, G), a, c = _run_batched(driver, tmp_path, "runb", xs, cs, po, co, 3)
+    assert f in (16, 32, 64) and G in (4, 8), (f, G)
+    for b in range(len(xs)):
+        ref = oracle.lloyd(xs[b], cs[b], max_iter=3)
+        np.testing.assert_array_equal(a[po[b]:po[b + 1]], ref["a"], err_msg=f"cloud {b}")
+        np.testing.assert_array_equal(c[co[b]:co[b + 1]], ref["c"], err_msg=f"cloud {b}")
+    (f2, G2), a2, c2 = _run_batched(driver, tmp_path, "runb", xs, cs, po, co, 3, leaf_size=32, cand_tile=4)
+    assert (f2, G2) == (32, 4)
+    np.testing.assert_array_equal(a2, a)
+    np.testing.assert_array_equal(c2, c)

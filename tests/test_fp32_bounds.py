@@ -17,7 +17,11 @@ properties the kernels rely on against canonical FP64 distances:
     is strictly farther in FP64 than the centroid that gave U, from every
     point of the box;
   * dist_lo(s) <= h implies s <= lo_inverse(h) (the FP64 recheck visits every
-    candidate that can still win).
+    candidate that can still win);
+  * inter_keep (the inter bound of Eq. (4) and (5)): a point, or every point
+    of a box, kept with its centroid c_a because it lies within half of the
+    FP32 distance from c_a to another centroid c_b is strictly nearer to c_a
+    than to c_b in FP64.
 
 Samples cover random, near-bisector, large-offset (|c| ~ 1e3) and tiny-scale
 data, a million cases per property.
@@ -125,6 +129,12 @@ def margin_safe(s1, s2, e, bias=0):
 def prune_threshold(U, e, bias=0):
     r = ((sqrt32(U + TAU, bias) * MARGIN_UP + F(2.0) * e) * MARGIN_UP * MARGIN_UP).astype(F)
     return (r * r * MARGIN_UP + TAU).astype(F)
+
+
+def inter_keep(cb_s, s, e, bias=0):
+    lhs = dist_lo(cb_s, F(2.0) * e, -bias)
+    rhs = ((F(2.0) * dist_hi(s, e, bias)).astype(F) * (F(1.0) + F(2.0 ** -14))).astype(F)
+    return lhs > rhs
 
 
 def d64(x, c):
@@ -288,3 +298,58 @@ def test_fma32_emulation_is_exact():
         cand = [np.nextafter(w32, F(-np.inf)), w32, np.nextafter(w32, F(np.inf))]
         best = min(cand, key=lambda v: (abs(Fraction(float(v)) - want), int(np.float32(v).view(np.uint32)) & 1))
         assert got[i] == best, i
+
+
+def _near_half(rng, d, n, kind):
+    """Owner a, other centroid b, and points x at distance ~ (0.4 .. 0.6) |a - b|
+    from a (the keep test's boundary is at one half)."""
+    scale = {"uniform": 1.0, "offset": 1.0, "tiny": 1e-6}[kind]
+    base = 1e3 if kind == "offset" else 0.0
+    a = base + rng.uniform(0, scale, (d, n))
+    b = a + rng.uniform(-0.05, 0.05, (d, n)) * scale
+    u = rng.standard_normal((d, n))
+    u /= np.sqrt(np.sum(u * u, 0))
+    r = np.sqrt(np.sum((b - a) ** 2, 0)) * rng.uniform(0.4, 0.6, n)
+    x = (a + u * r).astype(np.float32)
+    return x, a, b
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("kind", ["uniform", "offset", "tiny"])
+def test_inter_keep_point_implies_fp64_order(kind, d):
+    rng = np.random.default_rng(600 + 7 * d + ["uniform", "offset", "tiny"].index(kind))
+    x, a, b = _near_half(rng, d, N // 4, kind)
+    e = err_bound(cmax_bound(a, b))
+    ca, cb = a.astype(F), b.astype(F)
+    cb_s = sqdist32(ca, cb)
+    kept = 0
+    for bias in (-1, 0, 1):
+        keep = inter_keep(cb_s, sqdist32(x, ca), e, bias)
+        bad = keep & ~(d64(x, a) < d64(x, b))
+        assert not bad.any(), f"{bad.sum()} kept points not strictly nearer in FP64 ({kind}, d={d})"
+        kept += int(keep.sum())
+    assert kept > 0 and kept < 3 * x.shape[1]  # both outcomes occur near the boundary
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_inter_keep_box_implies_fp64_order(d):
+    rng = np.random.default_rng(700 + d)
+    n = N // 8
+    x0, a, b = _near_half(rng, d, n, "uniform")
+    ext = rng.uniform(0, 2e-3, (d, n))
+    lo = x0
+    hi = (x0.astype(np.float64) + ext).astype(np.float32)
+    e = err_bound(cmax_bound(a, b))
+    ca, cb = a.astype(F), b.astype(F)
+    keep = inter_keep(sqdist32(ca, cb), box_maxd(lo, hi, ca), e)
+    assert keep.sum() > 0
+    for trial in range(2 ** d + 4):
+        if trial < 2 ** d:
+            pick = [(trial >> i) & 1 for i in range(d)]
+            xs = np.stack([np.where(pick[i], hi[i], lo[i]) for i in range(d)])
+        else:
+            w = rng.uniform(0, 1, (d, n))
+            xs = (lo + w * (hi.astype(np.float64) - lo)).astype(np.float32)
+            xs = np.minimum(np.maximum(xs, lo), hi)
+        bad = keep & ~(d64(xs, a) < d64(xs, b))
+        assert not bad.any(), f"{bad.sum()} kept boxes with a point not strictly nearer to the owner"
