@@ -24,7 +24,7 @@ bool hip_ok(hipError_t e, const char *what)
     return false;
 }
 
-int64_t assign_blocks(const km_ctx *ctx);
+int64_t assign_blocks(km_ctx *ctx);
 
 static int ceil_log2(int64_t v)
 {
@@ -104,7 +104,8 @@ static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
         tree_layout(k, T);
         b += (size_t)T.nnodes * 32 + (size_t)k * 16;  // node boxes, tree-ordered centroids
     }
-    b += (size_t)k * (16 + 4 + d * 16 + 4); // c32, cval, acc, cnt
+    b += (size_t)k * (16 + 4 + d * 16 + 4 + d * 8); // c32, cval, acc, cnt, kmeans_run's centroids
+    b += (size_t)HIST_ROWS * (NSTAT + 1) * 8;        // per-step statistics rows of a run
     int64_t nblk = cfg->algo == KM_INDEXED ? L + HEAVY_BLOCKS : (n + 255) / 256; // statistics rows
     b += (size_t)nblk * NSTAT * 8 + (size_t)sse_blocks(n) * 8;
     if (cfg->algo == KM_INDEXED)
@@ -196,8 +197,9 @@ static km_status timed_step(km_ctx *ctx, const double *c_in, double *c_out, int3
     return s;
 }
 
-// kmeans_run's chunk of RUN_CHUNK steps on centroid array c, captured once
-// into a graph (on a private stream; launched on the context's stream).
+// kmeans_run's chunk of RUN_CHUNK steps on centroid array c (the context's
+// own), captured once into a graph (on a private stream; launched on the
+// context's stream).
 // Returns false when capture is not possible; the caller then launches the
 // steps one by one, with the same result.
 static bool chunk_graph(km_ctx *ctx, double *c)
@@ -412,8 +414,13 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     ctx->sse_part = ctx_alloc<double>(ctx, ctx->nblk_sse);
     ctx->stat_out = ctx_alloc<int64_t>(ctx, NSTAT);
     ctx->sse_out = ctx_alloc<double>(ctx, 1);
+    ctx->c_run = ctx_alloc<double>(ctx, (size_t)k * ctx->d);
+    if (hipMalloc((void **)&ctx->stat_hist, (size_t)HIST_ROWS * (NSTAT + 1) * sizeof(int64_t)) == hipSuccess)
+        ctx->hist_cap = HIST_ROWS;
+    else
+        ctx->stat_hist = nullptr;
     if (!ctx->a || !ctx->c32 || !ctx->cval || !ctx->cerr || !ctx->acc || !ctx->cnt || !ctx->stat_part ||
-        !ctx->sse_part || !ctx->stat_out || !ctx->sse_out) {
+        !ctx->sse_part || !ctx->stat_out || !ctx->sse_out || !ctx->c_run || !ctx->stat_hist) {
         kmeans_destroy(ctx);
         return alloc_fail(nullptr);
     }
@@ -516,6 +523,10 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
         kmeans_destroy(ctx);
         return KM_ERR_HIP;
     }
+    // kmeans_run's chunk of steps, captured now so that no run pays for it
+    // (a context that records phase times launches its steps one by one)
+    if (!(cfg->flags & KM_FLAG_TIMING))
+        (void)chunk_graph(ctx, ctx->c_run);
     if (cfg->workspace_limit_bytes > 0 && ctx->mem.bytes > (size_t)cfg->workspace_limit_bytes) {
         size_t used = ctx->mem.bytes;
         kmeans_destroy(ctx);
@@ -659,17 +670,21 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
     // are queued, so the device never waits for the host; at most RUN_AHEAD
     // chunks of steps that return at once follow the end of the run.
     km_status s = set_ctl(ctx, max_iter, stop_when_stable ? 1 : 0, 0);
+    double *c = ctx->c_run;
+    const size_t c_bytes = (size_t)ctx->k * ctx->d * sizeof(double);
+    if (s == KM_OK && !hip_ok(hipMemcpyAsync(c, c_inout, c_bytes, hipMemcpyDeviceToDevice, st), "kmeans_run: copy"))
+        s = KM_ERR_HIP;
     const bool timing = (ctx->cfg.flags & KM_FLAG_TIMING) != 0;
     int queued = 0; // chunks whose control copies are not yet looked at
     int nchunk = 0;
     for (int launched = 0; s == KM_OK && launched < max_iter;) {
         const int chunk = max_iter - launched < RUN_CHUNK ? max_iter - launched : RUN_CHUNK;
-        if (!timing && chunk == RUN_CHUNK && chunk_graph(ctx, c_inout)) {
+        if (!timing && chunk == RUN_CHUNK && chunk_graph(ctx, c)) {
             if (!hip_ok(hipGraphLaunch(ctx->chunk_exec, st), "kmeans_run: hipGraphLaunch"))
                 s = KM_ERR_HIP;
         } else {
             for (int i = 0; s == KM_OK && i < chunk; ++i)
-                s = timed_step(ctx, c_inout, c_inout, nullptr);
+                s = timed_step(ctx, c, c, nullptr);
         }
         launched += chunk;
         if (s != KM_OK || !stop_when_stable || launched >= max_iter)
@@ -699,7 +714,8 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
         return s;
     }
     int32_t *final_ctl = ctx->host_ctl + RUN_AHEAD * CTL_N;
-    if (!hip_ok(hipMemcpyAsync(final_ctl, ctx->ctl, CTL_N * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+    if (!hip_ok(hipMemcpyAsync(c_inout, c, c_bytes, hipMemcpyDeviceToDevice, st), "kmeans_run: copy") ||
+        !hip_ok(hipMemcpyAsync(final_ctl, ctx->ctl, CTL_N * sizeof(int32_t), hipMemcpyDeviceToHost, st),
                 "kmeans_run: control copy") ||
         !hip_ok(hipStreamSynchronize(st), "kmeans_run: hipStreamSynchronize"))
         return KM_ERR_HIP;

@@ -52,7 +52,8 @@ struct AssignArgs {
     const int64_t *leaf_sum;
     int32_t *leaf_own;
     int32_t *heavy;
-    int32_t *heavy_cnt;
+    int32_t *heavy_cnt; // their number (reset by the finalize kernel)
+    int64_t assign_wg;  // workgroups of the main pass
     const int32_t *group_leaf;
     const float4 *group_box;
     int64_t ngroups;
@@ -150,7 +151,8 @@ __device__ inline void combine_init(BlockCombine &bc)
     __syncthreads();
 }
 
-__device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const int64_t (&c)[NSTAT], int64_t row)
+template <class T>
+__device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const T (&c)[NSTAT], int64_t row)
 {
     const int lane = lane_id();
     int64_t mine = 0;
@@ -279,14 +281,13 @@ __device__ inline void fix_point(const float (&x)[D], bool on, const AssignArgs 
 {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        if (A.fix64) {
-            v0[i] = on ? fix_f32(x[i], A.S) : 0;
-            v1[i] = 0;
-        } else {
-            fix_split_f32(x[i], A.S, v0[i], v1[i]);
-            if (!on)
-                v0[i] = v1[i] = 0;
-        }
+        int64_t h = 0, l = 0; // one assignment per element: the array stays in registers
+        if (A.fix64)
+            h = fix_f32(x[i], A.S);
+        else
+            fix_split_f32(x[i], A.S, h, l);
+        v0[i] = on ? h : 0;
+        v1[i] = on ? l : 0;
     }
 }
 
@@ -504,19 +505,12 @@ __device__ inline Best2 scan_list(const float (&x)[D], const float *blo, const f
 // exact and in FP64 arithmetic).  Returns the centroid id (meaningful for
 // lanes with `need`).
 template <int D, class WS>
-__device__ inline int finish_point(const float (&x)[D], bool need, const Best2 &b, const float *blo,
-                                   const float *bhi, float thr, int sn, float e, const AssignArgs &A, const WS &sh,
-                                   int64_t (&st)[NSTAT])
+__device__ inline int recheck_points(const float (&x)[D], bool re, float s1, int id1,
+                                                        const float *blo, const float *bhi, float thr, int sn,
+                                                        float e, const AssignArgs &A, const WS &sh)
 {
     const int lane = lane_id();
     const int nch = (sn + WAVE - 1) / WAVE;
-    const float s1 = best2_s1(b), s2 = b.s2;
-    const int id1 = best2_id(b);
-    const bool re = need && !margin_safe(s1, s2, e);
-    const int nre = wave_count(re);
-    if (nre == 0)
-        return id1;
-    st[ST_RECHECK] += nre;
     double xd[D];
     for (int i = 0; i < D; ++i)
         xd[i] = (double)x[i];
@@ -555,8 +549,23 @@ __device__ inline int finish_point(const float (&x)[D], bool need, const Best2 &
 }
 
 template <int D, class WS>
+__device__ inline int finish_point(const float (&x)[D], bool need, const Best2 &b, const float *blo,
+                                   const float *bhi, float thr, int sn, float e, const AssignArgs &A, const WS &sh,
+                                   int32_t (&st)[NSTAT])
+{
+    const float s1 = best2_s1(b), s2 = b.s2;
+    const int id1 = best2_id(b);
+    const bool re = need && !margin_safe(s1, s2, e);
+    const int nre = wave_count(re);
+    if (nre == 0)
+        return id1;
+    st[ST_RECHECK] += nre;
+    return recheck_points<D>(x, re, s1, id1, blo, bhi, thr, sn, e, A, sh);
+}
+
+template <int D, class WS>
 __device__ inline int assign_point(const float (&x)[D], bool need, const float *blo, const float *bhi, float thr,
-                                   int sn, float e, const AssignArgs &A, const WS &sh, int64_t (&st)[NSTAT])
+                                   int sn, float e, const AssignArgs &A, const WS &sh, int32_t (&st)[NSTAT])
 {
     const Best2 b = scan_list<D>(x, blo, bhi, thr, sn, sh, 0, 1);
     return finish_point<D>(x, need, b, blo, bhi, thr, sn, e, A, sh, st);
@@ -568,7 +577,7 @@ __device__ inline int assign_point(const float (&x)[D], bool need, const float *
 // whose candidate list does not fit anywhere.
 template <int D>
 __device__ inline int scan_all(const float (&x)[D], bool need, float e, const AssignArgs &A, const TreeArgs *Tp,
-                               int64_t (&st)[NSTAT])
+                               int32_t (&st)[NSTAT])
 {
     const int lane = lane_id();
     const int64_t c0 = Tp->c0, c1 = Tp->c0 + Tp->k; // the cloud's centroids
@@ -611,15 +620,19 @@ __device__ inline int scan_all(const float (&x)[D], bool need, float e, const As
 }
 
 // A leaf as the wave sees it (uniform values).
+// oc / ocb: fl32 of the centroid of cluster `own` and its inter bound cb_s
+// (when own >= 0).
 struct LeafJob {
     int64_t l;
     int s, size, own;
     float lo[3], hi[3];
+    float oc[3], ocb;
 };
 
 // Per-leaf data held by lane t of the wave for leaf l0 + t of its group.
 struct LeafRegs {
     float lo[3], hi[3];
+    float oc[3], ocb;
     int start, size, own;
 };
 
@@ -635,7 +648,9 @@ __device__ inline LeafJob job_of(const LeafRegs &r, int t, int64_t l0)
     for (int i = 0; i < 3; ++i) {
         J.lo[i] = i < D ? rl_f(r.lo[i], t) : 0.0f;
         J.hi[i] = i < D ? rl_f(r.hi[i], t) : 0.0f;
+        J.oc[i] = i < D ? rl_f(r.oc[i], t) : 0.0f;
     }
+    J.ocb = rl_f(r.ocb, t);
     return J;
 }
 
@@ -649,6 +664,11 @@ __device__ inline LeafJob job_load(const AssignArgs &A, int64_t l)
     J.own = A.leaf_own[l];
     f4_to(A.leaf_box[2 * l], J.lo);
     f4_to(A.leaf_box[2 * l + 1], J.hi);
+    J.oc[0] = J.oc[1] = J.oc[2] = J.ocb = 0.0f;
+    if (J.own >= 0) {
+        f4_to(A.c32[J.own], J.oc);
+        J.ocb = A.cb_s[J.own];
+    }
     return J;
 }
 
@@ -675,36 +695,21 @@ __device__ inline LeafPts<D> load_pts(const AssignArgs &A, const LeafJob &J)
 }
 
 // A leaf with a single candidate j (Eq. (6): the whole leaf is assigned to
-// it without any distance evaluation).  A leaf that was wholly in one
-// cluster (or in none yet) moves its precomputed exact sum; a leaf of mixed
-// clusters moves the points that change (P: its points, loaded by the
-// caller when own == OWN_MIXED).
+// it without any distance evaluation) that was wholly in one cluster (or in
+// none yet): its precomputed exact sum moves, its points are not read.
 template <int D>
-__device__ void single_leaf(const AssignArgs &A, const LeafJob &J, int j, const LeafPts<D> &P, int64_t (&st)[NSTAT])
+__device__ void single_leaf(const AssignArgs &A, const LeafJob &J, int j, int32_t (&st)[NSTAT])
 {
     st[ST_SINGLE] += J.size;
     if (J.own == j)
         return; // already wholly in j
     const int lane = lane_id();
-    const bool valid = lane < J.size;
-    const int64_t p = (int64_t)J.s + lane;
-    if (J.own != OWN_MIXED) {
-        if (valid)
-            A.a[p] = j;
-        st[ST_CHANGED] += J.size;
-        if (J.own >= 0)
-            leaf_sum_add<D>(A, J.l, J.own, -1, J.size);
-        leaf_sum_add<D>(A, J.l, j, +1, J.size);
-    } else {
-        const bool ch = valid && P.a != j;
-        st[ST_CHANGED] += wave_count(ch);
-        int64_t v0[D], v1[D];
-        fix_point<D>(P.x, ch, A, v0, v1);
-        wave_scatter<D>(ch && P.a >= 0, P.a, -1, v0, v1, A);
-        wave_scatter<D>(ch, j, +1, v0, v1, A);
-        if (ch)
-            A.a[p] = j;
-    }
+    if (lane < J.size)
+        A.a[(int64_t)J.s + lane] = j;
+    st[ST_CHANGED] += J.size;
+    if (J.own >= 0)
+        leaf_sum_add<D>(A, J.l, J.own, -1, J.size);
+    leaf_sum_add<D>(A, J.l, j, +1, J.size);
     if (lane == 0)
         A.leaf_own[J.l] = j;
 }
@@ -712,21 +717,21 @@ __device__ void single_leaf(const AssignArgs &A, const LeafJob &J, int j, const 
 // Point-by-point decision of a leaf (lane = point, P loaded by the caller).
 // In a leaf wholly in cluster j, a point still within half the inter bound
 // of c_j keeps it (Eq. (4); c_j and cb_j are the same for the whole wave);
-// the other points are decided by `scan`.  Changed points move their exact
-// values between clusters; the leaf's common cluster is recorded for the
-// next step.
+// the other points are decided by `scan` (a single candidate of a leaf of
+// mixed clusters: every point goes to it).  Changed points move their exact
+// values between clusters (one inlined copy of the scatter, run for the
+// old and then the new cluster); the leaf's common cluster is recorded for
+// the next step.
 template <int D, class ScanFn>
 __device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafPts<D> &P, float e,
-                              int64_t evals_per_point, ScanFn scan, int64_t (&st)[NSTAT])
+                              int64_t evals_per_point, ScanFn scan, int32_t (&st)[NSTAT])
 {
     const int lane = lane_id();
     const bool valid = lane < J.size;
     const int64_t p = (int64_t)J.s + lane;
     bool pk = false;
     if (J.own >= 0) {
-        float cc[3];
-        f4_to(A.c32[J.own], cc);
-        pk = valid && inter_keep(A.cb_s[J.own], sqdist32<D>(P.x, cc), e);
+        pk = valid && inter_keep(J.ocb, sqdist32<D>(P.x, J.oc), e);
         st[ST_KEEP_PTS] += wave_count(pk);
     }
     const bool need = valid && !pk;
@@ -743,8 +748,9 @@ __device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafP
         st[ST_CHANGED] += nch;
         int64_t v0[D], v1[D];
         fix_point<D>(P.x, ch, A, v0, v1);
-        wave_scatter<D>(ch && P.a >= 0, P.a, -1, v0, v1, A);
-        wave_scatter<D>(ch, best, +1, v0, v1, A);
+#pragma unroll 1
+        for (int pass = 0; pass < 2; ++pass)
+            wave_scatter<D>(pass ? ch : ch && P.a >= 0, pass ? best : P.a, pass ? +1 : -1, v0, v1, A);
         if (ch)
             A.a[p] = best;
     }
@@ -756,7 +762,7 @@ __device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafP
 
 // A leaf whose candidate list does not fit: every point scans all k.
 template <int D>
-__device__ void leaf_all(const AssignArgs &A, const LeafJob &J, float e, const TreeArgs *Tp, int64_t (&st)[NSTAT])
+__device__ void leaf_all(const AssignArgs &A, const LeafJob &J, float e, const TreeArgs *Tp, int32_t (&st)[NSTAT])
 {
     const LeafPts<D> P = load_pts<D>(A, J);
     decide_points<D>(A, J, P, e, Tp->k,
@@ -769,46 +775,29 @@ __device__ inline bool needs_points(int m, int own, int j1, int heavy_m)
     return (m >= 2 && m <= heavy_m) || (m == 1 && own == OWN_MIXED && j1 != own);
 }
 
-// A leaf against the wave's list (sn entries), after its filter; P: its
-// points when needs_points() (loaded ahead by the caller).
+// A leaf against the wave's list (sn entries), after its filter found m >= 1
+// candidates (m == 0 cannot happen for a well-formed tree; callers send such
+// a leaf to the scan of all k regardless); P: its points when
+// needs_points() (loaded ahead by the caller).
 template <int D, class WS>
 __device__ void leaf_listed(const AssignArgs &A, const LeafJob &J, int m, int j1, float thr, int sn, float e,
-                            const WS &sh, const LeafPts<D> &P, const TreeArgs *Tp, int64_t (&st)[NSTAT])
+                            const WS &sh, const LeafPts<D> &P, int32_t (&st)[NSTAT])
 {
-    if (m == 0) { // cannot happen for a well-formed tree; stay correct regardless
-        leaf_all<D>(A, J, e, Tp, st);
-        return;
-    }
     st[ST_CANDS] += m;
-    if (m == 1) {
-        single_leaf<D>(A, J, j1, P, st);
+    if (m == 1 && J.own != OWN_MIXED) {
+        single_leaf<D>(A, J, j1, st);
         return;
     }
-    decide_points<D>(A, J, P, e, m,
+    if (m == 1)
+        st[ST_SINGLE] += J.size;
+    decide_points<D>(A, J, P, e, m == 1 ? 0 : m,
                      [&](const float (&x)[D], bool need) {
-                         return assign_point<D>(x, need, J.lo, J.hi, thr, sn, e, A, sh, st);
+                         return m == 1 ? j1 : assign_point<D>(x, need, J.lo, J.hi, thr, sn, e, A, sh, st);
                      },
                      st);
 }
 
-// One leaf with a search of its own (no group list), in a wave with LDS
-// capacities sw / fr; returns false if the list does not fit.
-template <int D, class WS>
-__device__ bool leaf_searched(const AssignArgs &A, const LeafJob &J, float e, WS &sh, int sw, int fr,
-                              const TreeArgs *Tp, int64_t (&st)[NSTAT])
-{
-    const int sn = wave_search<D>(J.lo, J.hi, Tp, e, sh, sw, fr);
-    if (sn < 0)
-        return false;
-    float thr;
-    int j1;
-    const int m = leaf_filter<D>(J.lo, J.hi, sn, e, sh, thr, j1);
-    const LeafPts<D> P = load_pts<D>(A, J);
-    leaf_listed<D>(A, J, m, j1, thr, sn, e, sh, P, Tp, st);
-    return true;
-}
-
-__device__ inline void defer_leaf(const AssignArgs &A, int64_t l, int64_t (&st)[NSTAT])
+__device__ inline void defer_leaf(const AssignArgs &A, int64_t l, int32_t (&st)[NSTAT])
 {
     st[ST_DEFERRED] += 1;
     if (lane_id() == 0)
@@ -841,7 +830,7 @@ __device__ inline void defer_leaf(const AssignArgs &A, int64_t l, int64_t (&st)[
 // does not fit, or that has more than heavy_m candidates, goes to the
 // per-leaf pass.  Results are the same on every path.
 template <int D>
-__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t (&st)[NSTAT])
+__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t (&st)[NSTAT])
 {
     const int lane = lane_id();
     const float e = err_bound(A.cmax_bits);
@@ -862,10 +851,11 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t
         r.own = A.leaf_own[l0 + lane];
     }
     bool keep = false;
+    r.oc[0] = r.oc[1] = r.oc[2] = r.ocb = 0.0f;
     if (lane < nl && r.own >= 0) {
-        float cc[3];
-        f4_to(A.c32[r.own], cc);
-        keep = inter_keep(A.cb_s[r.own], box_maxd<D>(r.lo, r.hi, cc), e);
+        f4_to(A.c32[r.own], r.oc);
+        r.ocb = A.cb_s[r.own];
+        keep = inter_keep(r.ocb, box_maxd<D>(r.lo, r.hi, r.oc), e);
     }
     const uint64_t kept = __ballot(keep);
     uint64_t todo = __ballot(lane < nl) & ~kept;
@@ -875,67 +865,75 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int64_t
         st[ST_GROUP_SKIP] += 1;
         return;
     }
-    // bounding box of the leaves still to decide
-    const bool mine = (todo >> lane) & 1ull;
-    float ulo[3] = {0.0f, 0.0f, 0.0f}, uhi[3] = {0.0f, 0.0f, 0.0f};
+    // Searches: one for the bounding box of every remaining leaf; if its
+    // list does not fit, one per leaf (a leaf whose own list still does not
+    // fit goes to the per-leaf pass).  One inlined copy of the search, the
+    // filters and the leaf decisions serves both.
+    bool per_leaf = false;
+    while (todo) {
+        const uint64_t unit = per_leaf ? (todo & (~todo + 1ull)) : todo; // leaves of this search
+        const bool mine = (unit >> lane) & 1ull;
+        float ulo[3] = {0.0f, 0.0f, 0.0f}, uhi[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        ulo[i] = wave_min_f32(mine ? r.lo[i] : INFINITY);
-        uhi[i] = -wave_min_f32(mine ? -r.hi[i] : INFINITY);
-    }
-    const int sn = wave_search<D>(ulo, uhi, Tp, e, sh, A.sw_main, A.fr_main);
-    if (sn < 0) {
-        // the list does not fit: search leaf by leaf
-        st[ST_GROUP_OVF] += 1;
-        for (uint64_t q = todo; q; q &= q - 1) {
-            const LeafJob J = job_of<D>(r, __ffsll((unsigned long long)q) - 1, l0);
-            if (!leaf_searched<D>(A, J, e, sh, A.sw_main, A.fr_main, Tp, st))
-                defer_leaf(A, J.l, st);
+        for (int i = 0; i < D; ++i) {
+            ulo[i] = wave_min_f32(mine ? r.lo[i] : INFINITY);
+            uhi[i] = -wave_min_f32(mine ? -r.hi[i] : INFINITY);
         }
-        return;
-    }
-    // filter every remaining leaf first; lane t keeps leaf t's results
-    float r_thr = 0.0f;
-    int r_m = 0, r_j = -1;
-    for (uint64_t q = todo; q; q &= q - 1) {
-        const int t = __ffsll((unsigned long long)q) - 1;
-        float blo[3], bhi[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            blo[i] = i < D ? rl_f(r.lo[i], t) : 0.0f;
-            bhi[i] = i < D ? rl_f(r.hi[i], t) : 0.0f;
-        }
-        float thr;
-        int j1;
-        const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
-        if (lane == t) {
-            r_thr = thr;
-            r_m = m;
-            r_j = j1;
-        }
-    }
-    // leaves whose decision reads their points: loaded one leaf ahead, so
-    // that the loads of the next leaf overlap the work on this one
-    uint64_t pts = __ballot(((todo >> lane) & 1ull) && needs_points(r_m, r.own, r_j, A.heavy_m));
-    LeafPts<D> Pn = {};
-    if (pts)
-        Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
-    for (uint64_t q = todo; q; q &= q - 1) {
-        const int t = __ffsll((unsigned long long)q) - 1;
-        const LeafJob J = job_of<D>(r, t, l0);
-        const int m = rl_i(r_m, t);
-        LeafPts<D> P = {};
-        if ((pts >> t) & 1ull) {
-            P = Pn;
-            pts &= pts - 1;
-            if (pts)
-                Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
-        }
-        if (m > A.heavy_m) { // a wave of its own in the per-leaf pass
-            defer_leaf(A, J.l, st);
+        const int sn = wave_search<D>(ulo, uhi, Tp, e, sh, A.sw_main, A.fr_main);
+        if (sn < 0) {
+            if (!per_leaf) {
+                st[ST_GROUP_OVF] += 1;
+                per_leaf = true;
+            } else {
+                defer_leaf(A, l0 + __ffsll((unsigned long long)unit) - 1, st);
+                todo &= ~unit;
+            }
             continue;
         }
-        leaf_listed<D>(A, J, m, rl_i(r_j, t), rl_f(r_thr, t), sn, e, sh, P, Tp, st);
+        todo &= ~unit;
+        // filter every leaf of the unit first; lane t keeps leaf t's results
+        float r_thr = 0.0f;
+        int r_m = 0, r_j = -1;
+        for (uint64_t q = unit; q; q &= q - 1) {
+            const int t = __ffsll((unsigned long long)q) - 1;
+            float blo[3], bhi[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                blo[i] = i < D ? rl_f(r.lo[i], t) : 0.0f;
+                bhi[i] = i < D ? rl_f(r.hi[i], t) : 0.0f;
+            }
+            float thr;
+            int j1;
+            const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
+            if (lane == t) {
+                r_thr = thr;
+                r_m = m;
+                r_j = j1;
+            }
+        }
+        // leaves whose decision reads their points: loaded one leaf ahead, so
+        // that the loads of the next leaf overlap the work on this one
+        uint64_t pts = __ballot(mine && needs_points(r_m, r.own, r_j, A.heavy_m));
+        LeafPts<D> Pn = {};
+        if (pts)
+            Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
+        for (uint64_t q = unit; q; q &= q - 1) {
+            const int t = __ffsll((unsigned long long)q) - 1;
+            const LeafJob J = job_of<D>(r, t, l0);
+            const int m = rl_i(r_m, t);
+            LeafPts<D> P = {};
+            if ((pts >> t) & 1ull) {
+                P = Pn;
+                pts &= pts - 1;
+                if (pts)
+                    Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
+            }
+            if (m == 0 || m > A.heavy_m) { // a wave of its own in the per-leaf pass
+                defer_leaf(A, J.l, st);
+                continue;
+            }
+            leaf_listed<D>(A, J, m, rl_i(r_j, t), rl_f(r_thr, t), sn, e, sh, P, st);
+        }
     }
 }
 
@@ -947,10 +945,11 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
     __shared__ WaveMain wsh[G_WAVES];
     __shared__ BlockCombine bc;
     combine_init(bc);
-    const int64_t g = (int64_t)blockIdx.x * G_WAVES + threadIdx.x / WAVE;
-    int64_t st[NSTAT] = {};
+    const int wv = uniform_int(threadIdx.x / WAVE); // the compiler then keeps group values in scalar registers
+    const int64_t g = (int64_t)blockIdx.x * G_WAVES + wv;
+    int32_t st[NSTAT] = {}; // one group's counts fit 32 bits (at most 512 points x 256 candidates)
     if (g < A.ngroups) // whole wave; nothing in group_work synchronises across waves
-        group_work<D>(g, A, wsh[threadIdx.x / WAVE], st);
+        group_work<D>(g, A, wsh[wv], st);
     combine_end(bc, A, st, blockIdx.x);
 }
 
@@ -978,11 +977,12 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
     __shared__ HeavyShared hs;
     __shared__ BlockCombine bc;
     combine_init(bc);
-    const int w = threadIdx.x / WAVE, lane = lane_id();
+    const int w = uniform_int(threadIdx.x / WAVE), lane = lane_id();
     const float e = err_bound(A.cmax_bits);
-    int64_t st[NSTAT] = {};
+    int64_t tot[NSTAT] = {}; // the workgroup's leaves; st: one leaf's counts (at most 64 points x 2^20 centroids)
     const int cnt = uniform_int(*A.heavy_cnt);
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        int32_t st[NSTAT] = {};
         const LeafJob J = job_load<D>(A, A.heavy[i]);
         const TreeArgs *Tp = A.trees + A.leaf_cloud[J.l];
         if (w == 0) {
@@ -1014,16 +1014,19 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
                                  st);
             }
         } else if (w == 0) {
-            if (sn < 0) {
+            if (sn < 0 || m == 0) {
                 leaf_all<D>(A, J, e, Tp, st);
             } else {
                 const LeafPts<D> P = load_pts<D>(A, J);
-                leaf_listed<D>(A, J, m, j1, thr, sn, e, hs.ws, P, Tp, st);
+                leaf_listed<D>(A, J, m, j1, thr, sn, e, hs.ws, P, st);
             }
         }
+#pragma unroll
+        for (int q = 0; q < NSTAT; ++q)
+            tot[q] += st[q];
         __syncthreads(); // the workgroup's LDS is free for the next leaf
     }
-    combine_end(bc, A, st, (A.ngroups + G_WAVES - 1) / G_WAVES + blockIdx.x);
+    combine_end(bc, A, tot, A.assign_wg + blockIdx.x);
 }
 
 // ------------------------------------------------------------- brute force
@@ -1206,6 +1209,8 @@ km_status run_sse(km_ctx *ctx, const double *c_in)
 }
 
 // ------------------------------------------------------------- driver
+int64_t assign_grid(km_ctx *ctx);
+
 static AssignArgs make_args(km_ctx *ctx, const double *c_in)
 {
     AssignArgs A;
@@ -1224,6 +1229,7 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in)
     A.leaf_own = ctx->leaf_own;
     A.heavy = ctx->heavy;
     A.heavy_cnt = ctx->heavy_cnt;
+    A.assign_wg = assign_grid(ctx);
     A.group_leaf = ctx->group_leaf;
     A.group_box = ctx->group_box;
     A.ngroups = ctx->ngroups;
@@ -1253,11 +1259,14 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in)
     return A;
 }
 
-// Rows of per-block (brute) or per-wave-group (indexed) statistics partials.
-int64_t assign_blocks(const km_ctx *ctx)
+// Workgroups of the indexed main pass (one wave per group).
+int64_t assign_grid(km_ctx *ctx) { return (ctx->ngroups + G_WAVES - 1) / G_WAVES; }
+
+// Rows of per-block (brute) or per-workgroup (indexed) statistics partials.
+int64_t assign_blocks(km_ctx *ctx)
 {
     if (ctx->cfg.algo == KM_INDEXED)
-        return (ctx->ngroups + G_WAVES - 1) / G_WAVES + HEAVY_BLOCKS;
+        return assign_grid(ctx) + HEAVY_BLOCKS;
     return (ctx->n + ASSIGN_THREADS - 1) / ASSIGN_THREADS;
 }
 
@@ -1268,7 +1277,7 @@ km_status run_assign(km_ctx *ctx, const double *c_in, hipEvent_t between)
     hipStream_t st = ctx->stream;
     AssignArgs A = make_args(ctx, c_in);
     unsigned nb = (unsigned)assign_blocks(ctx);
-    const unsigned nwg = (unsigned)((ctx->ngroups + G_WAVES - 1) / G_WAVES);
+    const unsigned nwg = ctx->cfg.algo == KM_INDEXED ? (unsigned)assign_grid(ctx) : 0u;
     const int D = ctx->d;
     if (ctx->cfg.algo == KM_INDEXED) {
         const unsigned nhw = (unsigned)HEAVY_BLOCKS;

@@ -60,6 +60,7 @@ enum CtlSlot {
 };
 constexpr int RUN_CHUNK = 8;  // steps per launch group (graph) of kmeans_run
 constexpr int RUN_AHEAD = 3;  // launch groups kmeans_run keeps queued while it waits for an earlier one
+constexpr int HIST_ROWS = 1024; // per-step statistics rows a context holds from the start
 
 // Common cluster of a leaf's points (leaf_own): a centroid id when every
 // point of the leaf is assigned to it, else one of these.
@@ -612,7 +613,9 @@ struct km_ctx {
     hipEvent_t chunk_ev[ekm::RUN_AHEAD] = {}; // completion of those copies
     int64_t *stat_hist = nullptr; // [hist_cap][NSTAT + 1] per-step statistics of a run
     int64_t hist_cap = 0;
-    // kmeans_run's captured chunk of RUN_CHUNK steps (one per centroid array)
+    // kmeans_run's centroids while it runs (the caller's array is copied in
+    // and out), and its chunk of RUN_CHUNK steps on them, captured once
+    double *c_run = nullptr;      // [k][d]
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t chunk_exec = nullptr;
     const double *chunk_c = nullptr;

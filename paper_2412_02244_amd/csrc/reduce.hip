@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) k_scatter_assign(const int32_t *a, const 
         out[perm[i]] = B == 1 ? a[i] : a[i] - (int32_t)c_off[cloud_of(pt_off, B, i)];
 }
 
-int64_t assign_blocks(const km_ctx *ctx);
+int64_t assign_blocks(km_ctx *ctx);
 
 km_status run_finalize(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, bool with_sse)
 {

@@ -401,6 +401,19 @@ hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int)
     return hipSuccess;
 }
 
+// A small emulated device: few persistent workgroups, so that each one
+// takes many groups from the work counter.
+hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int)
+{
+    *v = 4;
+    return hipSuccess;
+}
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, const void *, int, size_t)
+{
+    *n = 2;
+    return hipSuccess;
+}
+
 hipError_t hipGetDevice(int *d)
 {
     *d = 0;

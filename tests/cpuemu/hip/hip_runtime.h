@@ -192,6 +192,9 @@ struct hipDeviceProp_t {
     char gcnArchName[256];
 };
 hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int d);
+enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 63 };
+hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t a, int d);
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, const void *f, int threads, size_t lds);
 hipError_t hipEventCreate(hipEvent_t *e);
 hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned flags);
 enum { hipEventDefault = 0, hipEventDisableTiming = 2 };
