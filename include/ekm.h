@@ -69,6 +69,10 @@ typedef enum {
 #define KM_FLAG_SMALL_LISTS 4u /* testing aid: tiny candidate-list capacities, so that every
                                   fallback path (group overflow, deferred leaves, scan of all
                                   k centroids) runs; results are unchanged, only slower */
+#define KM_FLAG_CELL_LEAVES 8u /* indexed path: a leaf is the largest Morton cell holding at
+                                  most f points (default: f consecutive points of a group
+                                  cell, the largest Morton cell holding at most G * f points,
+                                  so that leaves are full); results are unchanged */
 
 /* Phases of one step, in order, for kmeans_phase_times / kmeans_step_times. */
 #define KM_PHASE_TREE 0     /* fl32 centroids, norm bound, centroid tree, inter bounds */
@@ -87,9 +91,10 @@ typedef struct km_config {
     int32_t leaf_size;   /* f: maximum points per leaf, 0 = default (64; autotuned by
                             kmeans_run_batched); must be 0 or a power of two in [8, 64] */
     int32_t cand_tile;   /* indexed path: leaves sharing one candidate list (the tile of
-                            candidates staged in LDS), 1..8, 0 = default (8; autotuned by
-                            kmeans_run_batched); brute path: centroids staged in LDS per
-                            tile, 64..2048, 0 = default (1024) */
+                            candidates staged in LDS), 1..8, 0 = default (6 in 2D, 8 in 3D
+                            or with KM_FLAG_CELL_LEAVES; autotuned by kmeans_run_batched);
+                            brute path: centroids staged in LDS per tile, 64..2048,
+                            0 = default (1024) */
     uint32_t flags;      /* KM_FLAG_* */
     int64_t workspace_limit_bytes; /* 0 = unlimited; otherwise kmeans_init fails with
                                       KM_ERR_OOM if the workspace would exceed it */
@@ -183,14 +188,14 @@ EKM_API km_status kmeans_init_batched(km_ctx **out, const km_config *cfg, const 
                               const int64_t *pt_offs, const int64_t *c_offs, int32_t B, void *stream);
 
 /* `iters` Lloyd iterations of B independent clouds (layout as for
- * kmeans_init_batched), in one call: the index is built, the steps run in
- * captured HIP graphs of several steps each, the assignment is written and the
- * workspace released.
+ * kmeans_init_batched), in one call: the index is built, the `iters` steps
+ * (every launch of each covering all clouds) are captured into one HIP graph
+ * and launched once, the assignment is written and the workspace released.
  *   c_inout:    device, k x d FP64 (all clouds' centroids), refined in place.
  *   assign_out: device, n int32 (cloud-local ids, caller order), or NULL.
  *   cfg->leaf_size == 0 / cfg->cand_tile == 0: chosen by timing a few
- *   iterations of each candidate (leaf sizes 16, 32, 64; 4 or 8 leaves per
- *   candidate list) on up to 64 evenly spaced clouds; the choice is cached
+ *   iterations of each candidate (leaf sizes 16, 32, 64; 4, 6 or 8 leaves
+ *   per candidate list) on up to 64 evenly spaced clouds; the choice is cached
  *   per GPU architecture and workload class (d, typical cloud size and
  *   centroid count) for the rest of the process.
  *   tuned_out:  host int32[2] receiving the leaf size and the leaves per

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     KM_ERR_UNSUPPORTED,
     KM_F32,
     KM_F64,
+    KM_FLAG_CELL_LEAVES,
     KM_FLAG_SMALL_LISTS,
     KM_FLAG_SSE,
     KM_FLAG_TIMING,

@@ -23,6 +23,7 @@ KM_BRUTE, KM_INDEXED = 0, 1
 KM_FLAG_SSE = 1
 KM_FLAG_TIMING = 2
 KM_FLAG_SMALL_LISTS = 4
+KM_FLAG_CELL_LEAVES = 8
 PHASES = ("tree", "assign", "deferred", "update")
 
 EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_init_batched", "kmeans_step", "kmeans_run",

@@ -352,7 +352,7 @@ km_status kmeans_destroy(km_ctx *ctx)
 // Context over B clouds (B = 1: kmeans_init) with point / centroid offsets
 // pt_off / c_off ([B + 1], host), already validated.
 static km_status init_context(km_ctx **out, const km_config *cfg, const void *points, int B, const int64_t *pt_off,
-                              const int64_t *c_off, void *stream)
+                              const int64_t *c_off, void *stream, bool capture_chunk = true)
 {
     const int64_t n = pt_off[B], k = c_off[B];
     if (cfg->workspace_limit_bytes > 0 && workspace_bytes(cfg, n, k) > (size_t)cfg->workspace_limit_bytes) {
@@ -372,7 +372,9 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     ctx->k = k;
     ctx->d = cfg->d;
     ctx->f = cfg->leaf_size ? cfg->leaf_size : 64;
-    ctx->G = cfg->algo == KM_INDEXED && cfg->cand_tile ? cfg->cand_tile : GROUP_LEAVES;
+    ctx->G = cfg->algo == KM_INDEXED && cfg->cand_tile
+                 ? cfg->cand_tile
+                 : (cfg->d == 2 && !(cfg->flags & KM_FLAG_CELL_LEAVES) ? DEFAULT_G_2D : GROUP_LEAVES);
     ctx->tile = cfg->algo == KM_BRUTE && cfg->cand_tile ? cfg->cand_tile : 1024;
     ctx->stream = (hipStream_t)stream;
     ctx->small_lists = (cfg->flags & KM_FLAG_SMALL_LISTS) ? 1 : 0;
@@ -525,7 +527,7 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     }
     // kmeans_run's chunk of steps, captured now so that no run pays for it
     // (a context that records phase times launches its steps one by one)
-    if (!(cfg->flags & KM_FLAG_TIMING))
+    if (capture_chunk && !(cfg->flags & KM_FLAG_TIMING))
         (void)chunk_graph(ctx, ctx->c_run);
     if (cfg->workspace_limit_bytes > 0 && ctx->mem.bytes > (size_t)cfg->workspace_limit_bytes) {
         size_t used = ctx->mem.bytes;
@@ -738,6 +740,58 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
     return KM_OK;
 }
 
+// A fixed-length run of `iters` steps captured into one graph and launched
+// once (the device loop control still counts the steps).  Returns false,
+// having launched nothing, if the steps cannot be captured; otherwise s is
+// the run's status.
+static bool run_captured(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t iters, km_status &s)
+{
+    if (iters == 0 || (ctx->cfg.flags & KM_FLAG_TIMING))
+        return false;
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        ctx->cap_stream = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    hipStream_t st = ctx->stream;
+    hipStream_t saved = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    bool ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        for (int i = 0; ok && i < iters; ++i)
+            ok = step_body(ctx, ctx->c_run, ctx->c_run, nullptr, nullptr) == KM_OK;
+        ok = hipStreamEndCapture(ctx->cap_stream, &g) == hipSuccess && ok && g;
+    }
+    ctx->stream = saved;
+    if (ok)
+        ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g)
+        (void)hipGraphDestroy(g);
+    if (!ok) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const size_t c_bytes = (size_t)ctx->k * ctx->d * sizeof(double);
+    s = set_ctl(ctx, iters, 0, 0);
+    if (s == KM_OK &&
+        (!hip_ok(hipMemcpyAsync(ctx->c_run, c_inout, c_bytes, hipMemcpyDeviceToDevice, st), "run: copy") ||
+         !hip_ok(hipGraphLaunch(ex, st), "run: hipGraphLaunch") ||
+         !hip_ok(hipMemcpyAsync(c_inout, ctx->c_run, c_bytes, hipMemcpyDeviceToDevice, st), "run: copy") ||
+         !hip_ok(hipStreamSynchronize(st), "run: hipStreamSynchronize")))
+        s = KM_ERR_HIP;
+    (void)hipGraphExecDestroy(ex);
+    if (s == KM_OK)
+        s = set_ctl(ctx, 0, 0, 1);
+    if (s == KM_OK) {
+        ctx->steps_done += iters;
+        if (assign_out)
+            s = scatter_assignment(ctx, assign_out);
+    }
+    return true;
+}
+
 // Leaf size and leaves per candidate list for a batched run (f, G): the
 // given ones, or the fastest of the candidates over 3 timed iterations
 // (after one warm-up iteration) on up to 64 evenly spaced clouds.  Cached
@@ -753,7 +807,7 @@ static km_status autotune(const km_config *cfg, const void *points, const int64_
     if (cfg->cand_tile)
         Gs.push_back(cfg->cand_tile);
     else
-        Gs = {4, 8};
+        Gs = {4, 6, 8};
     f_out = fs[0];
     G_out = Gs[0];
     if (fs.size() * Gs.size() == 1)
@@ -769,7 +823,8 @@ static km_status autotune(const km_config *cfg, const void *points, const int64_
     const std::string key = std::string(prop.gcnArchName) + "/d" + std::to_string(cfg->d) + "/n" +
                             std::to_string(lg((double)pt_offs[B] / B)) + "/k" +
                             std::to_string(lg((double)c_offs[B] / B)) + "/f" + std::to_string(cfg->leaf_size) +
-                            "/t" + std::to_string(cfg->cand_tile);
+                            "/t" + std::to_string(cfg->cand_tile) +
+                            ((cfg->flags & KM_FLAG_CELL_LEAVES) ? "/cells" : "");
     {
         std::lock_guard<std::mutex> lock(mu);
         auto it = cache.find(key);
@@ -880,9 +935,10 @@ km_status kmeans_run_batched(const void *points, const int64_t *pt_offs, double 
         c2.cand_tile = G;
     }
     km_ctx *ctx = nullptr;
-    if ((s = init_context(&ctx, &c2, points, B, pt_offs, c_offs, stream)) != KM_OK)
+    if ((s = init_context(&ctx, &c2, points, B, pt_offs, c_offs, stream, false)) != KM_OK)
         return s;
-    s = kmeans_run(ctx, c_inout, assign_out, iters, 0, nullptr, nullptr);
+    if (!run_captured(ctx, c_inout, assign_out, iters, s)) // capture not possible: the same steps in chunks
+        s = kmeans_run(ctx, c_inout, assign_out, iters, 0, nullptr, nullptr);
     if (s == KM_OK && !hip_ok(hipStreamSynchronize(st), "kmeans_run_batched: hipStreamSynchronize"))
         s = KM_ERR_HIP;
     if (s == KM_OK && tuned_out) {

@@ -18,6 +18,7 @@ namespace ekm {
 constexpr int WAVE = 64;
 constexpr int MAX_LEAF = 64;     // a leaf fits one wave
 constexpr int GROUP_LEAVES = 8;  // most consecutive leaves sharing one centroid-tree descent (one wave)
+constexpr int DEFAULT_G_2D = 6;  // default leaves per group in 2D (3D: GROUP_LEAVES); measured on 1e6 hotspot points
 // Leaves with more candidates than this go to the per-leaf pass.  At the
 // main pass's list capacity, only leaves whose candidate list does not fit
 // are deferred (measured: deferring crowded leaves cost more in the extra

@@ -3,9 +3,13 @@
 // subsection on indexes over spatial vectors and centroids).
 //
 // GPU realisation: points are sorted along a Morton curve over the data
-// bounding box, and cut into leaves that are the largest Morton cells
-// (quadtree / octree cells) holding at most f points.  A leaf is a contiguous
-// run of the sorted points, so a wave reads it with coalesced loads; each leaf
+// bounding box and cut into group cells, the largest Morton cells (quadtree /
+// octree cells) holding at most G * f points; each group cell is cut into
+// leaves of f consecutive points (the last one shorter), so that a leaf fills
+// a 64-lane wave.  (With KM_FLAG_CELL_LEAVES a leaf is instead the largest
+// Morton cell holding at most f points: tighter boxes, fewer points per
+// leaf.)  A leaf is a contiguous run of the sorted points, so a wave reads it
+// with coalesced loads; each leaf
 // keeps its exact FP32 bounding box (the box plays the role of the paper's
 // ball pivot and radius) and the exact fixed-point sum of its points, so a
 // leaf that falls wholly into one cluster updates that cluster's sum without
@@ -371,6 +375,38 @@ __global__ void __launch_bounds__(256) k_group_boxes(const float4 *leaf_box, con
 }
 
 // ------------------------------------------------------------ driver
+// Packed leaves.  cflag / cscan: group-cell starts over the sorted points and
+// their exclusive scan; cell_first[c]: the first point of cell c.
+__global__ void __launch_bounds__(256) k_cell_first_pt(const uint32_t *cflag, const uint32_t *cscan, int64_t n,
+                                                       int32_t *cell_first)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cflag[i])
+        cell_first[cscan[i]] = (int32_t)i;
+}
+
+// lflag[i] = 1 iff point i starts a leaf: its rank in its group cell is a multiple of f.
+__global__ void __launch_bounds__(256) k_packed_flags(const uint32_t *cflag, const uint32_t *cscan,
+                                                      const int32_t *cell_first, int64_t n, int f, uint32_t *lflag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int64_t c = (int64_t)cscan[i] + cflag[i] - 1;
+    lflag[i] = ((i - cell_first[c]) % f) == 0 ? 1u : 0u;
+}
+
+// Group c = the leaves of group cell c (lscan: exclusive scan of the leaf starts).
+__global__ void __launch_bounds__(256) k_packed_groups(const int32_t *cell_first, const uint32_t *lscan,
+                                                       int64_t ncells, int64_t L, int32_t *group_leaf)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells)
+        group_leaf[c] = (int32_t)lscan[cell_first[c]];
+    if (c == 0)
+        group_leaf[ncells] = (int32_t)L;
+}
+
 static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 template <class T, int D>
@@ -497,11 +533,47 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
     ctx->xs = xs;
     hipLaunchKernelGGL((k_gather<T, D>), dim3(nblocks(n, 256)), dim3(256), 0, st, x, ctx->perm, n, xs);
     // 4. leaves
-    hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n, ctx->f, flag, pt_off, B);
+    const bool packed = sizeof(T) == 4 && ctx->cfg.algo == KM_INDEXED && !(ctx->cfg.flags & KM_FLAG_CELL_LEAVES);
+    uint32_t last[2];
+    int64_t ncells = 0;
+    int32_t *cell_first = nullptr; // packed leaves: first point of each group cell (temporary)
+    uint32_t *lflag = nullptr;
+    struct FreeOnExit { // hipFree waits for the queued kernels that use the buffer
+        void *p = nullptr;
+        ~FreeOnExit()
+        {
+            if (p)
+                (void)hipFree(p);
+        }
+    } tmp_guard;
+    if (packed) {
+        // group cells over the points, then leaves of f points inside each
+        hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n, ctx->G * ctx->f,
+                           flag, pt_off, B);
+        if (!hip_ok(hipMemcpyAsync(scan, flag, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy") ||
+            !hip_ok(exclusive_scan_u32(scan, n, scan_tmp, st), "scan") ||
+            !hip_ok(hipMemcpyAsync(&last[0], scan + n - 1, 4, hipMemcpyDeviceToHost, st), "copy") ||
+            !hip_ok(hipMemcpyAsync(&last[1], flag + n - 1, 4, hipMemcpyDeviceToHost, st), "copy") ||
+            !hip_ok(hipStreamSynchronize(st), "sync"))
+            return KM_ERR_HIP;
+        ncells = (int64_t)last[0] + last[1];
+        if (hipMalloc((void **)&cell_first, (size_t)(ncells + n) * sizeof(int32_t)) != hipSuccess) {
+            set_error("kmeans_init: device allocation failed");
+            return KM_ERR_OOM;
+        }
+        tmp_guard.p = cell_first;
+        lflag = (uint32_t *)(cell_first + ncells);
+        hipLaunchKernelGGL(k_cell_first_pt, dim3(nblocks(n, 256)), dim3(256), 0, st, flag, scan, n, cell_first);
+        hipLaunchKernelGGL(k_packed_flags, dim3(nblocks(n, 256)), dim3(256), 0, st, flag, scan,
+                           (const int32_t *)cell_first, n, ctx->f, lflag);
+        flag = lflag;
+    } else {
+        hipLaunchKernelGGL((k_leaf_flags<D>), dim3(nblocks(n, 256)), dim3(256), 0, st, skeys, n, ctx->f, flag, pt_off,
+                           B);
+    }
     if (!hip_ok(hipMemcpyAsync(scan, flag, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy") ||
         !hip_ok(exclusive_scan_u32(scan, n, scan_tmp, st), "scan"))
         return KM_ERR_HIP;
-    uint32_t last[2];
     if (!hip_ok(hipMemcpyAsync(&last[0], scan + n - 1, 4, hipMemcpyDeviceToHost, st), "copy") ||
         !hip_ok(hipMemcpyAsync(&last[1], flag + n - 1, 4, hipMemcpyDeviceToHost, st), "copy") ||
         !hip_ok(hipStreamSynchronize(st), "sync"))
@@ -526,6 +598,26 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
                            ctx->leaf_start, L, S, (float4 *)ctx->leaf_box, ctx->leaf_sum);
         hipLaunchKernelGGL(k_leaf_clouds, dim3(nblocks(L, 256)), dim3(256), 0, st, (const int32_t *)ctx->leaf_start,
                            L, pt_off, B, ctx->leaf_cloud);
+    }
+    if (packed) { // one group per group cell
+        ctx->ngroups = ncells;
+        ctx->group_leaf = ctx_alloc<int32_t>(ctx, ncells + 1);
+        ctx->group_box = ctx_alloc<float4>(ctx, 2 * ncells);
+        ctx->group_cloud = ctx_alloc<int32_t>(ctx, ncells);
+        if (!ctx->group_leaf || !ctx->group_box || !ctx->group_cloud) {
+            set_error("kmeans_init: device allocation failed");
+            return KM_ERR_OOM;
+        }
+        hipLaunchKernelGGL(k_packed_groups, dim3(nblocks(ncells, 256)), dim3(256), 0, st, (const int32_t *)cell_first,
+                           (const uint32_t *)scan, ncells, L, ctx->group_leaf);
+        hipLaunchKernelGGL(k_group_boxes, dim3(nblocks(ncells, 256)), dim3(256), 0, st, (const float4 *)ctx->leaf_box,
+                           (const int32_t *)ctx->group_leaf, ncells, ctx->group_box);
+        hipLaunchKernelGGL(k_group_clouds, dim3(nblocks(ncells, 256)), dim3(256), 0, st,
+                           (const int32_t *)ctx->group_leaf, ncells, (const int32_t *)ctx->leaf_cloud,
+                           ctx->group_cloud);
+        if (!hip_ok(hipStreamSynchronize(st), "sync"))
+            return KM_ERR_HIP;
+    } else if (sizeof(T) == 4 && ctx->cfg.algo == KM_INDEXED) {
         // wave groups (flag and scan are free again; the leaf-level arrays
         // live in scan, which holds n >= 4L words once L <= n/4, else in a
         // temporary): group cells are the leaf rule at G times the leaf size

@@ -11,20 +11,14 @@
 // afresh and they are cleared here.  The last block folds the per-block
 // statistics and objective partials in a fixed order, so the reported
 // counters and objective are deterministic.
-#include "ekm_internal.hpp"
+#include "finalize.hpp"
 
 namespace ekm {
 
-constexpr int FIN_THREADS = 256;
-
 template <int D>
 __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, double *c_out, int64_t k, int64_t *acc,
-                                                          int32_t *cnt, int S, int reset, int64_t nblk,
-                                                          const int64_t *stat_part, int64_t nsse,
-                                                          const double *sse_part, int64_t *stat_out, double *sse_out,
-                                                          unsigned *cmax_bits, unsigned *drift_max,
-                                                          int32_t *heavy_cnt, int64_t nclusterblocks, int32_t *ctl,
-                                                          int64_t *stat_hist, int64_t hist_cap)
+                                                          int32_t *cnt, int S, int reset, int64_t nclusterblocks,
+                                                          FinStats F)
 {
     // The cluster blocks run even when the run is over: every kernel of such
     // a step returned at once, so the sums are those of the last real step
@@ -33,82 +27,14 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, do
     // alone sets CTL_STOP, tests it, so no block races that write.
     if ((int64_t)blockIdx.x < nclusterblocks) {
         int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (j >= k)
-            return;
-        int32_t c = cnt[j];
-        int64_t *aj = acc + j * D * 2;
-        double out[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const __int128 V = ((__int128)aj[2 * i] << 32) + (__int128)aj[2 * i + 1];
-            out[i] = c > 0 ? fix128_to_double(V, S) / (double)c // IEEE-correct FP64 division
-                           : c_in[j * D + i];
-            // normal form (hi, lo in [0, 2^32)) for the next step's updates, or cleared
-            aj[2 * i] = reset ? 0 : (int64_t)(V >> 32);
-            aj[2 * i + 1] = reset ? 0 : (int64_t)(V & (__int128)0xffffffff);
-        }
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-            c_out[j * D + i] = out[i];
-        if (reset)
-            cnt[j] = 0;
+        if (j < k)
+            fin_cluster<D>(j, c_in, c_out, acc, cnt, S, reset);
         return;
     }
-    // statistics block: each thread folds whole rows (NSTAT counters) of the
-    // per-block partials, then a fixed-shape tree combines the threads
-    if (ctl[CTL_STOP])
+    if (F.ctl[CTL_STOP])
         return; // a step after the end of the run: nothing to record
-    __shared__ long long red[NSTAT][FIN_THREADS];
-    __shared__ double dred[FIN_THREADS];
-    long long acc8[NSTAT];
-    for (int q = 0; q < NSTAT; ++q)
-        acc8[q] = 0;
-    for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x) {
-        const longlong2 *row = (const longlong2 *)(stat_part + b * NSTAT);
-#pragma unroll
-        for (int q = 0; q < NSTAT / 2; ++q) {
-            longlong2 v = row[q];
-            acc8[2 * q] += v.x;
-            acc8[2 * q + 1] += v.y;
-        }
-    }
-    double s = 0.0;
-    for (int64_t b = threadIdx.x; b < nsse; b += blockDim.x)
-        s += sse_part[b];
-    for (int q = 0; q < NSTAT; ++q)
-        red[q][threadIdx.x] = acc8[q];
-    dred[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            for (int q = 0; q < NSTAT; ++q)
-                red[q][threadIdx.x] += red[q][threadIdx.x + o];
-            dred[threadIdx.x] += dred[threadIdx.x + o];
-        }
-        __syncthreads();
-    }
-    const int it = ctl[CTL_RUN_ITERS]; // this step's index in the run
-    if (threadIdx.x < NSTAT) {
-        stat_out[threadIdx.x] = red[threadIdx.x][0];
-        if (stat_hist && it < hist_cap)
-            stat_hist[it * (NSTAT + 1) + threadIdx.x] = red[threadIdx.x][0];
-    }
-    if (threadIdx.x == 0) {
-        if (stat_hist && it < hist_cap)
-            stat_hist[it * (NSTAT + 1) + NSTAT] = __double_as_longlong(dred[0]);
-        // loop control: the run ends after max_iter steps, or at the first
-        // step t >= 2 whose assignment equals that of step t - 1
-        ctl[CTL_RUN_ITERS] = it + 1;
-        ctl[CTL_STEPS] += 1;
-        if (it + 1 >= ctl[CTL_MAX_ITER] || (ctl[CTL_STABLE] && it >= 1 && red[ST_CHANGED][0] == 0))
-            ctl[CTL_STOP] = 1;
-        *sse_out = dred[0];
-        *cmax_bits = 0u; // the next centroid tree recomputes the norm bound
-        if (drift_max)
-            *drift_max = 0u; // and the largest drift
-        if (heavy_cnt)
-            *heavy_cnt = 0; // the deferred-leaf list of the next step starts empty
-    }
+    __shared__ FinShared fs;
+    fin_stats(fs, F);
 }
 
 // Caller order and cloud-local centroid ids (position i of the Morton order
@@ -124,23 +50,36 @@ __global__ void __launch_bounds__(256) k_scatter_assign(const int32_t *a, const 
 
 int64_t assign_blocks(km_ctx *ctx);
 
+FinStats fin_stats_args(km_ctx *ctx, bool with_sse)
+{
+    FinStats F;
+    F.nblk = assign_blocks(ctx);
+    F.stat_part = ctx->stat_part;
+    F.nsse = with_sse ? ctx->nblk_sse : 0;
+    F.sse_part = ctx->sse_part;
+    F.stat_out = ctx->stat_out;
+    F.sse_out = ctx->sse_out;
+    F.cmax_bits = (unsigned *)ctx->cerr;
+    F.drift_max = ctx->drift_max;
+    F.heavy_cnt = ctx->heavy_cnt;
+    F.ctl = ctx->ctl;
+    F.stat_hist = ctx->stat_hist;
+    F.hist_cap = ctx->hist_cap;
+    return F;
+}
+
 km_status run_finalize(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, bool with_sse)
 {
     hipStream_t st = ctx->stream;
     int64_t ncb = (ctx->k + FIN_THREADS - 1) / FIN_THREADS;
-    int64_t nblk = assign_blocks(ctx);
     const int reset = ctx->cfg.algo == KM_INDEXED ? 0 : 1;
-    const int64_t nsse = with_sse ? ctx->nblk_sse : 0;
+    const FinStats F = fin_stats_args(ctx, with_sse);
     if (ctx->d == 2)
         hipLaunchKernelGGL(k_finalize<2>, dim3((unsigned)(ncb + 1)), dim3(FIN_THREADS), 0, st, c_in, c_out, ctx->k,
-                           ctx->acc, ctx->cnt, ctx->S, reset, nblk, ctx->stat_part, nsse, ctx->sse_part,
-                           ctx->stat_out, ctx->sse_out, (unsigned *)ctx->cerr, ctx->drift_max, ctx->heavy_cnt, ncb,
-                           ctx->ctl, ctx->stat_hist, ctx->hist_cap);
+                           ctx->acc, ctx->cnt, ctx->S, reset, ncb, F);
     else
         hipLaunchKernelGGL(k_finalize<3>, dim3((unsigned)(ncb + 1)), dim3(FIN_THREADS), 0, st, c_in, c_out, ctx->k,
-                           ctx->acc, ctx->cnt, ctx->S, reset, nblk, ctx->stat_part, nsse, ctx->sse_part,
-                           ctx->stat_out, ctx->sse_out, (unsigned *)ctx->cerr, ctx->drift_max, ctx->heavy_cnt, ncb,
-                           ctx->ctl, ctx->stat_hist, ctx->hist_cap);
+                           ctx->acc, ctx->cnt, ctx->S, reset, ncb, F);
     if (!hip_ok(hipGetLastError(), "finalize launch"))
         return KM_ERR_HIP;
     return assign_out ? scatter_assignment(ctx, assign_out) : KM_OK;

@@ -102,6 +102,7 @@ __attribute__((noinline)) inline void emu_wave_barrier()
 #define __builtin_amdgcn_mov_dpp(v, ctrl, rm, bm, bc) emu_update_dpp(0, (v), (ctrl), (rm), (bm), (bc))
 #define __builtin_amdgcn_wave_barrier() emu_wave_barrier()
 #define __builtin_amdgcn_fence(order, scope) ((void)(order), (void)(scope))
+inline void __threadfence() { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
 
 template <class T>
 __attribute__((noinline)) T emu_shfl(int op, T v, int a)

@@ -71,7 +71,7 @@ def test_batched_64_clouds_every_iteration(ekm):
     ar = torch.empty_like(a)
     f, G = ekm.kmeans_run_batched(xt, po, cr, co, 30, assign_out=ar)
     _say(f"batched 64: tuned leaf size {f}, leaves per list {G}")
-    assert f in (16, 32, 64) and G in (4, 8)
+    assert f in (16, 32, 64) and G in (4, 6, 8)
     np.testing.assert_array_equal(ar.cpu().numpy(), ah)
     np.testing.assert_array_equal(cr.cpu().numpy(), ch)
 
