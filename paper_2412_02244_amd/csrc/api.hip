@@ -98,7 +98,8 @@ static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
     int64_t L = n;                        // leaves <= n
     b += (size_t)(L + 1) * 4;             // leaf_start
     if (cfg->algo == KM_INDEXED) {
-        b += (size_t)L * (32 + d * 16 + 4 + 4) + 4;    // leaf box, exact sums, previous cluster, deferred list
+        b += (size_t)L * (32 + d * 16 + 4 + 4 + 4) + 4; // leaf box, exact sums, previous cluster, distance
+                                                         // bound, deferred list
         b += (size_t)L * 36 + 4;                      // groups (at most one per leaf): boxes, first leaves
         TreeArgs T;
         tree_layout(k, T);
@@ -473,6 +474,7 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
             return KM_ERR_HIP;
         }
         ctx->leaf_own = ctx_alloc<int32_t>(ctx, L);
+        ctx->leaf_r = ctx_alloc<float>(ctx, L);
         ctx->heavy = ctx_alloc<int32_t>(ctx, L);
         ctx->heavy_cnt = ctx_alloc<int32_t>(ctx, 1);
         ctx->cb_s = ctx_alloc<unsigned>(ctx, k);
@@ -480,12 +482,13 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
         ctx->drift = ctx_alloc<float>(ctx, k);
         ctx->drift_max = ctx_alloc<unsigned>(ctx, 1);
         ctx->c_prev = ctx_alloc<double>(ctx, (size_t)k * ctx->d);
-        if (!ctx->leaf_own || !ctx->heavy || !ctx->heavy_cnt || !ctx->cb_s ||
+        if (!ctx->leaf_own || !ctx->leaf_r || !ctx->heavy || !ctx->heavy_cnt || !ctx->cb_s ||
             !ctx->cb_hi || !ctx->drift || !ctx->drift_max || !ctx->c_prev) {
             kmeans_destroy(ctx);
             return alloc_fail(nullptr);
         }
         if (!hip_ok(hipMemsetD32Async(ctx->leaf_own, OWN_NONE, L, st), "hipMemsetD32Async") ||
+            !hip_ok(hipMemsetD32Async(ctx->leaf_r, 0x7f800000, L, st), "hipMemsetD32Async") || // +inf
             !hip_ok(hipMemsetAsync(ctx->heavy, 0, L * sizeof(int32_t), st), "hipMemsetAsync") ||
             !hip_ok(hipMemsetAsync(ctx->drift_max, 0, sizeof(unsigned), st), "hipMemsetAsync") ||
             !hip_ok(hipMemsetAsync(ctx->heavy_cnt, 0, sizeof(int32_t), st), "hipMemsetAsync")) {

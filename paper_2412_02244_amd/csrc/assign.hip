@@ -51,6 +51,8 @@ struct AssignArgs {
     const float4 *leaf_box;
     const int64_t *leaf_sum;
     int32_t *leaf_own;
+    float *leaf_r;                // [L] per-leaf distance bounds (see km_ctx::leaf_r)
+    const unsigned *drift_max;    // bound on the largest centroid drift since the previous step (float bits)
     int32_t *heavy;
     int32_t *heavy_cnt; // their number (reset by the finalize kernel)
     int64_t assign_wg;  // workgroups of the main pass
@@ -188,9 +190,15 @@ __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 // and the last step the centroids of the kept buckets.  U is the smallest
 // box-to-node max-distance seen at any level (a valid bound: every node
 // holds a centroid).  Each lane keeps the min-distances of its entries in
-// its own LDS slots between the two passes of a level.
+// its own LDS slots between the two passes of a level.  thr_cap caps the
+// pruning threshold: prune_threshold_r of a bound on the exact distance from
+// every point of the box to its previous centroid, carried over from the
+// previous step with the centroids' drift (Eq. (9)'s use of drift), or
+// +inf.  A centroid beyond it is farther than every point's previous
+// centroid, so it is nobody's nearest.
 template <int D, class WS>
-__device__ int wave_search(const float *lo, const float *hi, const TreeArgs *Tp, float e, WS &sh, int sw, int fr)
+__device__ int wave_search(const float *lo, const float *hi, const TreeArgs *Tp, float e, WS &sh, int sw, int fr,
+                           float thr_cap)
 {
     const int npar = fr / TREE_BUCKET;
     const TreeArgs &T = *Tp; // the cloud's tree (read through the pointer: no register copy)
@@ -219,7 +227,7 @@ __device__ int wave_search(const float *lo, const float *hi, const TreeArgs *Tp,
             sh.fm[i] = m; // read back by this lane only
         }
         U = fminf(U, wave_min_f32(Ul));
-        const float thr = prune_threshold(U, e);
+        const float thr = fminf(prune_threshold(U, e), thr_cap);
         const int nxt = cur ^ 1;
         int cnt = 0;
         for (int i0 = 0; i0 < F; i0 += WAVE) {
@@ -257,7 +265,7 @@ __device__ int wave_search(const float *lo, const float *hi, const TreeArgs *Tp,
         sh.fm[i] = m;
     }
     U = fminf(U, wave_min_f32(Ul));
-    const float thr = prune_threshold(U, e);
+    const float thr = fminf(prune_threshold(U, e), thr_cap);
     int cnt = 0;
     for (int i0 = 0; i0 < F; i0 += WAVE) {
         const int i = i0 + lane;
@@ -397,10 +405,13 @@ __device__ inline float4 list_entry(const WS &sh, int j, int sn)
 
 // Candidate filter of one leaf box against the wave's list (sn entries):
 // returns the candidate count m, the id of the first candidate (the only
-// one when m == 1) and the threshold for the later mask passes.
+// one when m == 1), the threshold for the later mask passes (capped by
+// thr_cap, as in wave_search) and U, the smallest FP32 box max-distance to
+// a list entry (every point of the box is within exact distance
+// dist_hi(U, e) of that entry, hence of its own nearest centroid).
 template <int D, class WS>
 __device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, float e, const WS &sh,
-                                  float &thr, int &j1)
+                                  float thr_cap, float &thr, int &j1, float &Uout)
 {
     const int lane = lane_id();
     const int nch = (sn + WAVE - 1) / WAVE;
@@ -413,7 +424,8 @@ __device__ inline int leaf_filter(const float *blo, const float *bhi, int sn, fl
         if (j < sn)
             U = fminf(U, box_maxd<D>(blo, bhi, cc));
     }
-    thr = prune_threshold(wave_min_f32(U), e);
+    Uout = wave_min_f32(U);
+    thr = fminf(prune_threshold(Uout, e), thr_cap);
     int m = 0;
     j1 = -1;
     for (int c = 0; c < nch; ++c) {
@@ -551,9 +563,10 @@ __device__ inline int recheck_points(const float (&x)[D], bool re, float s1, int
 template <int D, class WS>
 __device__ inline int finish_point(const float (&x)[D], bool need, const Best2 &b, const float *blo,
                                    const float *bhi, float thr, int sn, float e, const AssignArgs &A, const WS &sh,
-                                   int32_t (&st)[NSTAT])
+                                   int32_t (&st)[NSTAT], float &s1out)
 {
     const float s1 = best2_s1(b), s2 = b.s2;
+    s1out = s1;
     const int id1 = best2_id(b);
     const bool re = need && !margin_safe(s1, s2, e);
     const int nre = wave_count(re);
@@ -565,10 +578,11 @@ __device__ inline int finish_point(const float (&x)[D], bool need, const Best2 &
 
 template <int D, class WS>
 __device__ inline int assign_point(const float (&x)[D], bool need, const float *blo, const float *bhi, float thr,
-                                   int sn, float e, const AssignArgs &A, const WS &sh, int32_t (&st)[NSTAT])
+                                   int sn, float e, const AssignArgs &A, const WS &sh, int32_t (&st)[NSTAT],
+                                   float &s1)
 {
     const Best2 b = scan_list<D>(x, blo, bhi, thr, sn, sh, 0, 1);
-    return finish_point<D>(x, need, b, blo, bhi, thr, sn, e, A, sh, st);
+    return finish_point<D>(x, need, b, blo, bhi, thr, sn, e, A, sh, st, s1);
 }
 
 // FP32 scan of all k centroids (fl32 copies, 64 at a time in registers, the
@@ -577,7 +591,7 @@ __device__ inline int assign_point(const float (&x)[D], bool need, const float *
 // whose candidate list does not fit anywhere.
 template <int D>
 __device__ inline int scan_all(const float (&x)[D], bool need, float e, const AssignArgs &A, const TreeArgs *Tp,
-                               int32_t (&st)[NSTAT])
+                               int32_t (&st)[NSTAT], float &s1out)
 {
     const int lane = lane_id();
     const int64_t c0 = Tp->c0, c1 = Tp->c0 + Tp->k; // the cloud's centroids
@@ -606,6 +620,7 @@ __device__ inline int scan_all(const float (&x)[D], bool need, float e, const As
     for (int u = 1; u < SCAN_ILP; ++u)
         bs[0] = best2_merge(bs[0], bs[u]);
     const float s1 = best2_s1(bs[0]), s2 = bs[0].s2;
+    s1out = s1;
     int best = best2_id(bs[0]);
     const bool re = need && !margin_safe(s1, s2, e);
     st[ST_RECHECK] += wave_count(re);
@@ -622,17 +637,21 @@ __device__ inline int scan_all(const float (&x)[D], bool need, float e, const As
 // A leaf as the wave sees it (uniform values).
 // oc / ocb: fl32 of the centroid of cluster `own` and its inter bound cb_s
 // (when own >= 0).
+// R: bound on the exact distance from each of its points to its previous
+// centroid at this step's positions (+inf if unknown).
 struct LeafJob {
     int64_t l;
     int s, size, own;
     float lo[3], hi[3];
     float oc[3], ocb;
+    float R;
 };
 
 // Per-leaf data held by lane t of the wave for leaf l0 + t of its group.
 struct LeafRegs {
     float lo[3], hi[3];
     float oc[3], ocb;
+    float R;
     int start, size, own;
 };
 
@@ -651,6 +670,7 @@ __device__ inline LeafJob job_of(const LeafRegs &r, int t, int64_t l0)
         J.oc[i] = i < D ? rl_f(r.oc[i], t) : 0.0f;
     }
     J.ocb = rl_f(r.ocb, t);
+    J.R = rl_f(r.R, t);
     return J;
 }
 
@@ -669,6 +689,7 @@ __device__ inline LeafJob job_load(const AssignArgs &A, int64_t l)
         f4_to(A.c32[J.own], J.oc);
         J.ocb = A.cb_s[J.own];
     }
+    J.R = bound_add(A.leaf_r[l], __uint_as_float(*A.drift_max));
     return J;
 }
 
@@ -697,13 +718,16 @@ __device__ inline LeafPts<D> load_pts(const AssignArgs &A, const LeafJob &J)
 // A leaf with a single candidate j (Eq. (6): the whole leaf is assigned to
 // it without any distance evaluation) that was wholly in one cluster (or in
 // none yet): its precomputed exact sum moves, its points are not read.
+// R: the leaf's new distance bound.
 template <int D>
-__device__ void single_leaf(const AssignArgs &A, const LeafJob &J, int j, int32_t (&st)[NSTAT])
+__device__ void single_leaf(const AssignArgs &A, const LeafJob &J, int j, float R, int32_t (&st)[NSTAT])
 {
     st[ST_SINGLE] += J.size;
+    const int lane = lane_id();
+    if (lane == 0)
+        A.leaf_r[J.l] = R;
     if (J.own == j)
         return; // already wholly in j
-    const int lane = lane_id();
     if (lane < J.size)
         A.a[(int64_t)J.s + lane] = j;
     st[ST_CHANGED] += J.size;
@@ -720,8 +744,11 @@ __device__ void single_leaf(const AssignArgs &A, const LeafJob &J, int j, int32_
 // the other points are decided by `scan` (a single candidate of a leaf of
 // mixed clusters: every point goes to it).  Changed points move their exact
 // values between clusters (one inlined copy of the scatter, run for the
-// old and then the new cluster); the leaf's common cluster is recorded for
-// the next step.
+// old and then the new cluster); the leaf's common cluster and its distance
+// bound (each point's exact distance to its centroid is at most dist_hi of
+// its FP32 distance to the centroid kept, or to the FP32 best, which is no
+// nearer than the chosen one) are recorded for the next step.  `scan`
+// returns the decision and the FP32 best distance.
 template <int D, class ScanFn>
 __device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafPts<D> &P, float e,
                               int64_t evals_per_point, ScanFn scan, int32_t (&st)[NSTAT])
@@ -730,18 +757,29 @@ __device__ void decide_points(const AssignArgs &A, const LeafJob &J, const LeafP
     const bool valid = lane < J.size;
     const int64_t p = (int64_t)J.s + lane;
     bool pk = false;
+    float s = 0.0f; // FP32 distance to the centroid kept or found
     if (J.own >= 0) {
-        pk = valid && inter_keep(J.ocb, sqdist32<D>(P.x, J.oc), e);
+        s = sqdist32<D>(P.x, J.oc);
+        pk = valid && inter_keep(J.ocb, s, e);
         st[ST_KEEP_PTS] += wave_count(pk);
     }
     const bool need = valid && !pk;
     const int nneed = wave_count(need);
+    int best = P.a;
+    if (nneed) {
+        st[ST_EVALS] += evals_per_point * nneed;
+        float s1;
+        const int b = scan(P.x, need, s1);
+        if (need) {
+            best = b;
+            s = s1;
+        }
+    }
+    const float R = -wave_min_f32(valid ? -dist_hi(s, e) : 0.0f);
+    if (lane == 0)
+        A.leaf_r[J.l] = R;
     if (nneed == 0)
         return; // every point keeps its cluster: nothing changes
-    st[ST_EVALS] += evals_per_point * nneed;
-    int best = scan(P.x, need);
-    if (!need)
-        best = P.a;
     const bool ch = valid && best != P.a;
     const int nch = wave_count(ch);
     if (nch) {
@@ -766,33 +804,33 @@ __device__ void leaf_all(const AssignArgs &A, const LeafJob &J, float e, const T
 {
     const LeafPts<D> P = load_pts<D>(A, J);
     decide_points<D>(A, J, P, e, Tp->k,
-                     [&](const float (&x)[D], bool need) { return scan_all<D>(x, need, e, A, Tp, st); }, st);
-}
-
-// Whether a leaf's decision reads its points (m: its candidate count).
-__device__ inline bool needs_points(int m, int own, int j1, int heavy_m)
-{
-    return (m >= 2 && m <= heavy_m) || (m == 1 && own == OWN_MIXED && j1 != own);
+                     [&](const float (&x)[D], bool need, float &s1) { return scan_all<D>(x, need, e, A, Tp, st, s1); },
+                     st);
 }
 
 // A leaf against the wave's list (sn entries), after its filter found m >= 1
 // candidates (m == 0 cannot happen for a well-formed tree; callers send such
-// a leaf to the scan of all k regardless); P: its points when
-// needs_points() (loaded ahead by the caller).
+// a leaf to the scan of all k regardless) and U (see leaf_filter); P: its
+// points (loaded by the caller; not read for a single candidate of a leaf
+// wholly in one cluster).
 template <int D, class WS>
-__device__ void leaf_listed(const AssignArgs &A, const LeafJob &J, int m, int j1, float thr, int sn, float e,
-                            const WS &sh, const LeafPts<D> &P, int32_t (&st)[NSTAT])
+__device__ void leaf_listed(const AssignArgs &A, const LeafJob &J, int m, int j1, float thr, float U, int sn,
+                            float e, const WS &sh, const LeafPts<D> &P, int32_t (&st)[NSTAT])
 {
     st[ST_CANDS] += m;
     if (m == 1 && J.own != OWN_MIXED) {
-        single_leaf<D>(A, J, j1, st);
+        single_leaf<D>(A, J, j1, dist_hi(U, e), st);
         return;
     }
     if (m == 1)
         st[ST_SINGLE] += J.size;
     decide_points<D>(A, J, P, e, m == 1 ? 0 : m,
-                     [&](const float (&x)[D], bool need) {
-                         return m == 1 ? j1 : assign_point<D>(x, need, J.lo, J.hi, thr, sn, e, A, sh, st);
+                     [&](const float (&x)[D], bool need, float &s1) {
+                         if (m == 1) {
+                             s1 = U; // the box max-distance bounds every point's distance
+                             return j1;
+                         }
+                         return assign_point<D>(x, need, J.lo, J.hi, thr, sn, e, A, sh, st, s1);
                      },
                      st);
 }
@@ -837,11 +875,13 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
     const TreeArgs *Tp = A.trees + A.group_cloud[g];
     const int64_t l0 = A.group_leaf[g];
     const int nl = A.group_leaf[g + 1] - (int)l0; // 1..GROUP_LEAVES
+    const float drift = __uint_as_float(*A.drift_max);
     LeafRegs r;
     for (int i = 0; i < 3; ++i)
         r.lo[i] = r.hi[i] = 0.0f;
     r.start = r.size = 0;
     r.own = OWN_NONE;
+    r.R = 0.0f;
     if (lane < nl) {
         const float4 bl = A.leaf_box[2 * (l0 + lane)], bh = A.leaf_box[2 * (l0 + lane) + 1];
         f4_to(bl, r.lo);
@@ -849,13 +889,17 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
         r.start = A.leaf_start[l0 + lane];
         r.size = A.leaf_start[l0 + lane + 1] - r.start;
         r.own = A.leaf_own[l0 + lane];
+        r.R = bound_add(A.leaf_r[l0 + lane], drift); // the last step's bound, moved with the centroids
     }
     bool keep = false;
     r.oc[0] = r.oc[1] = r.oc[2] = r.ocb = 0.0f;
     if (lane < nl && r.own >= 0) {
         f4_to(A.c32[r.own], r.oc);
         r.ocb = A.cb_s[r.own];
-        keep = inter_keep(r.ocb, box_maxd<D>(r.lo, r.hi, r.oc), e);
+        const float s = box_maxd<D>(r.lo, r.hi, r.oc);
+        keep = inter_keep(r.ocb, s, e);
+        if (keep)
+            A.leaf_r[l0 + lane] = dist_hi(s, e); // every point is within this of c_own
     }
     const uint64_t kept = __ballot(keep);
     uint64_t todo = __ballot(lane < nl) & ~kept;
@@ -864,6 +908,21 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
     if (!todo) {
         st[ST_GROUP_SKIP] += 1;
         return;
+    }
+    // The points of every leaf still to decide, loaded at once: one round
+    // trip for the group, overlapping the search below (slot t holds this
+    // lane's point of leaf l0 + t).  The leaf loop then issues no loads after
+    // its stores and atomics, so it never waits for those to complete.
+    float gx[GROUP_LEAVES][D];
+    int ga[GROUP_LEAVES];
+#pragma unroll
+    for (int t = 0; t < GROUP_LEAVES; ++t) {
+        const int64_t p = (int64_t)rl_i(r.start, t) + lane;
+        const bool v = ((todo >> t) & 1ull) && lane < rl_i(r.size, t);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            gx[t][i] = v ? ((const float *)A.xs)[(int64_t)i * A.n + p] : 0.0f;
+        ga[t] = v ? A.a[p] : -1;
     }
     // Searches: one for the bounding box of every remaining leaf; if its
     // list does not fit, one per leaf (a leaf whose own list still does not
@@ -879,7 +938,8 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
             ulo[i] = wave_min_f32(mine ? r.lo[i] : INFINITY);
             uhi[i] = -wave_min_f32(mine ? -r.hi[i] : INFINITY);
         }
-        const int sn = wave_search<D>(ulo, uhi, Tp, e, sh, A.sw_main, A.fr_main);
+        const float Ru = -wave_min_f32(mine ? -r.R : 0.0f); // every point of the unit is within Ru of a centroid
+        const int sn = wave_search<D>(ulo, uhi, Tp, e, sh, A.sw_main, A.fr_main, prune_threshold_r(Ru, e));
         if (sn < 0) {
             if (!per_leaf) {
                 st[ST_GROUP_OVF] += 1;
@@ -892,7 +952,7 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
         }
         todo &= ~unit;
         // filter every leaf of the unit first; lane t keeps leaf t's results
-        float r_thr = 0.0f;
+        float r_thr = 0.0f, r_u = 0.0f;
         int r_m = 0, r_j = -1;
         for (uint64_t q = unit; q; q &= q - 1) {
             const int t = __ffsll((unsigned long long)q) - 1;
@@ -902,37 +962,34 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
                 blo[i] = i < D ? rl_f(r.lo[i], t) : 0.0f;
                 bhi[i] = i < D ? rl_f(r.hi[i], t) : 0.0f;
             }
-            float thr;
+            float thr, U;
             int j1;
-            const int m = leaf_filter<D>(blo, bhi, sn, e, sh, thr, j1);
+            const int m = leaf_filter<D>(blo, bhi, sn, e, sh, prune_threshold_r(rl_f(r.R, t), e), thr, j1, U);
             if (lane == t) {
                 r_thr = thr;
                 r_m = m;
                 r_j = j1;
+                r_u = U;
             }
         }
-        // leaves whose decision reads their points: loaded one leaf ahead, so
-        // that the loads of the next leaf overlap the work on this one
-        uint64_t pts = __ballot(mine && needs_points(r_m, r.own, r_j, A.heavy_m));
-        LeafPts<D> Pn = {};
-        if (pts)
-            Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
         for (uint64_t q = unit; q; q &= q - 1) {
             const int t = __ffsll((unsigned long long)q) - 1;
             const LeafJob J = job_of<D>(r, t, l0);
             const int m = rl_i(r_m, t);
-            LeafPts<D> P = {};
-            if ((pts >> t) & 1ull) {
-                P = Pn;
-                pts &= pts - 1;
-                if (pts)
-                    Pn = load_pts<D>(A, job_of<D>(r, __ffsll((unsigned long long)pts) - 1, l0));
-            }
+            LeafPts<D> P; // slot t (selected with a uniform index: the slots stay in registers)
+#pragma unroll
+            for (int u = 0; u < GROUP_LEAVES; ++u)
+                if (u == t) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        P.x[i] = gx[u][i];
+                    P.a = ga[u];
+                }
             if (m == 0 || m > A.heavy_m) { // a wave of its own in the per-leaf pass
                 defer_leaf(A, J.l, st);
                 continue;
             }
-            leaf_listed<D>(A, J, m, rl_i(r_j, t), rl_f(r_thr, t), sn, e, sh, P, st);
+            leaf_listed<D>(A, J, m, rl_i(r_j, t), rl_f(r_thr, t), rl_f(r_u, t), sn, e, sh, P, st);
         }
     }
 }
@@ -986,16 +1043,17 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
         const LeafJob J = job_load<D>(A, A.heavy[i]);
         const TreeArgs *Tp = A.trees + A.leaf_cloud[J.l];
         if (w == 0) {
-            const int sn = wave_search<D>(J.lo, J.hi, Tp, e, hs.ws, A.sw_heavy, A.fr_heavy);
+            const int sn =
+                wave_search<D>(J.lo, J.hi, Tp, e, hs.ws, A.sw_heavy, A.fr_heavy, prune_threshold_r(J.R, e));
             if (lane == 0)
                 hs.sn = sn;
         }
         __syncthreads();
         const int sn = uniform_int(hs.sn);
-        float thr = 0.0f;
+        float thr = 0.0f, U = 0.0f;
         int j1 = -1, m = 0;
-        if (sn >= 0)
-            m = leaf_filter<D>(J.lo, J.hi, sn, e, hs.ws, thr, j1); // every wave: the same m
+        if (sn >= 0) // every wave: the same m
+            m = leaf_filter<D>(J.lo, J.hi, sn, e, hs.ws, prune_threshold_r(J.R, e), thr, j1, U);
         if (m >= 2) {
             const LeafPts<D> P = load_pts<D>(A, J);
             const Best2 b = scan_list<D>(P.x, J.lo, J.hi, thr, sn, hs.ws, w, G_WAVES);
@@ -1008,8 +1066,8 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
                     t = best2_merge(t, Best2{hs.key[u][lane], hs.s2[u][lane]});
                 st[ST_CANDS] += m;
                 decide_points<D>(A, J, P, e, m,
-                                 [&](const float (&x)[D], bool need) {
-                                     return finish_point<D>(x, need, t, J.lo, J.hi, thr, sn, e, A, hs.ws, st);
+                                 [&](const float (&x)[D], bool need, float &s1) {
+                                     return finish_point<D>(x, need, t, J.lo, J.hi, thr, sn, e, A, hs.ws, st, s1);
                                  },
                                  st);
             }
@@ -1018,7 +1076,7 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
                 leaf_all<D>(A, J, e, Tp, st);
             } else {
                 const LeafPts<D> P = load_pts<D>(A, J);
-                leaf_listed<D>(A, J, m, j1, thr, sn, e, hs.ws, P, st);
+                leaf_listed<D>(A, J, m, j1, thr, U, sn, e, hs.ws, P, st);
             }
         }
 #pragma unroll
@@ -1227,6 +1285,8 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in)
     A.leaf_box = (const float4 *)ctx->leaf_box;
     A.leaf_sum = ctx->leaf_sum;
     A.leaf_own = ctx->leaf_own;
+    A.leaf_r = ctx->leaf_r;
+    A.drift_max = ctx->drift_max;
     A.heavy = ctx->heavy;
     A.heavy_cnt = ctx->heavy_cnt;
     A.assign_wg = assign_grid(ctx);

@@ -149,15 +149,26 @@ __device__ inline float lo_inverse(float h, float e)
 // centroid whose FP32 value is >= s2.
 __device__ inline bool margin_safe(float s1, float s2, float e) { return dist_lo(s2, e) > dist_hi(s1, e); }
 
-// Pruning threshold on FP32 squared box distances.  With U = an FP32
-// max-distance from the box to some existing centroid, any centroid whose
-// FP32 min-distance to the box exceeds prune_threshold(U, e) is strictly
-// farther (in FP64) than that centroid from every point of the box.
-__device__ inline float prune_threshold(float U, float e)
+// Pruning threshold on FP32 squared box distances from an exact-distance
+// bound: when every point of the box is within exact distance R of some
+// existing centroid (not necessarily the same one), any centroid whose FP32
+// min-distance to the box exceeds prune_threshold_r(R, e) is strictly
+// farther (in exact and in FP64 distance) from every point of the box than
+// that point's centroid: its exact distance exceeds (R + e) (1 + 2^-16)^2
+// less e, and the relative gap dwarfs the FP64 rounding.
+__device__ inline float prune_threshold_r(float R, float e)
 {
-    float r = (sqrtf(U + TAU) * MARGIN_UP + 2.0f * e) * MARGIN_UP * MARGIN_UP;
+    float r = (R + e) * MARGIN_UP * MARGIN_UP;
     return r * r * MARGIN_UP + TAU;
 }
+
+// The same with U = an FP32 max-distance from the box to one existing
+// centroid (its exact distance from every point is at most dist_hi(U, e)).
+__device__ inline float prune_threshold(float U, float e) { return prune_threshold_r(dist_hi(U, e), e); }
+
+// Upper bound (FP32, rounded up) on R + drift for exact-distance bounds R
+// and centroid drift bounds (non-negative; +inf stays +inf).
+__device__ inline float bound_add(float R, float drift) { return (R + drift) * MARGIN_UP; }
 
 // Inter bound (Eq. (4), (5)): every point within exact distance r of c_j,
 // where every other centroid is at exact distance >= cb from c_j, is
@@ -574,6 +585,8 @@ struct km_ctx {
     float *leaf_box = nullptr;    // [L][2][4] lo xyz pad, hi xyz pad
     int64_t *leaf_sum = nullptr;  // [L][d][2] exact fixed-point sums
     int32_t *leaf_own = nullptr;  // [L] cluster of every point of the leaf, OWN_MIXED or OWN_NONE
+    float *leaf_r = nullptr;      // [L] bound on the exact distance from each point of the leaf to its
+                                  //     centroid at the last step's positions (+inf before the first)
     int32_t *heavy = nullptr;     // [L] ids of the leaves deferred to the per-leaf pass of this step
     int32_t *heavy_cnt = nullptr; // [1] their number (reset by the finalize kernel)
     // A1: centroid tree

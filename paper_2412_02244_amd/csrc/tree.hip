@@ -180,10 +180,12 @@ __device__ inline float err_of(float cmax) { return cmax * 0x1p-24f * (1.0f + 0x
 template <int D>
 __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all, const TreeArgs *trees,
                                                              const Grid *grids, float4 *c32, unsigned *cmax_bits,
-                                                             unsigned *cb_s, const int32_t *ctl)
+                                                             unsigned *cb_s, double *c_prev_all, unsigned *drift_max,
+                                                             const int32_t *ctl)
 {
     if (ctl[CTL_STOP])
         return; // the run is over (the whole workgroup returns)
+    const int have_prev = uniform_int(ctl[CTL_STEPS] > 0 ? 1 : 0);
     const TreeArgs &T = trees[blockIdx.x];
     const Grid g = grids[blockIdx.x];
     const int64_t c0 = T.c0, k = T.k;
@@ -197,15 +199,23 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
     uint32_t *id2 = key2 + SMALL_K;           // [SMALL_K]
     uint32_t *wcnt = id2 + SMALL_K;           // [TREE_WAVES][256]
     uint32_t *base = wcnt + TREE_WAVES * 256; // [256]
-    __shared__ float red[TREE_WAVES];
+    __shared__ float red[TREE_WAVES], dred[TREE_WAVES];
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
     const int kk = (int)k;
     const int shift = key_bits(D) - 16; // sort on the top 16 bits
-    float nb = 0.0f;
+    float nb = 0.0f, dm = 0.0f;
+    double *c_prev = c_prev_all + c0 * D;
     for (int j = tid; j < kk; j += TREE_THREADS) {
         float4 q4;
         uint32_t kb;
         nb = fmaxf(nb, centroid_prep_one<D>(c, j, g, q4, kb));
+        // drift since the previous step (bounds of the previous step's
+        // assignment carry over with it), then the centroid becomes the
+        // previous one of the next step
+        if (have_prev)
+            dm = fmaxf(dm, drift_bound<D>(c + j * D, c_prev + j * D));
+        for (int i = 0; i < D; ++i)
+            c_prev[j * D + i] = c[j * D + i];
         cq[j] = q4;
         c32[c0 + j] = q4;
         cb_s[c0 + j] = 0x7f800000u; // +inf: k_cb_pairs takes the minimum
@@ -214,14 +224,20 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
         id[j] = resort ? (uint32_t)j : (uint32_t)(__float_as_int(T.cs[j].w) - (int)c0);
     }
     nb = -wave_min_f32(-nb);
-    if (lane == 0)
+    dm = -wave_min_f32(-dm);
+    if (lane == 0) {
         red[wid] = nb;
+        dred[wid] = dm;
+    }
     __syncthreads();
     if (tid == 0) {
-        float m = 0.0f;
-        for (int w = 0; w < TREE_WAVES; ++w)
+        float m = 0.0f, d = 0.0f;
+        for (int w = 0; w < TREE_WAVES; ++w) {
             m = fmaxf(m, red[w]);
+            d = fmaxf(d, dred[w]);
+        }
         atomicMax(cmax_bits, __float_as_uint(m)); // over all clouds (non-negative floats order like their bits)
+        atomicMax(drift_max, __float_as_uint(d));
     }
     if (resort) {
         // two stable passes over 8-bit digits
@@ -518,13 +534,15 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
         const unsigned nb = (unsigned)ctx->B;
         if (ctx->d == 2) {
             hipLaunchKernelGGL(k_tree_small<2>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(), st, c_in,
-                               (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s, hp);
+                               (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s,
+                               ctx->c_prev, ctx->drift_max, hp);
             hipLaunchKernelGGL(k_cb_pairs<2>, gb, dim3(CB_THREADS), 0, st, (const float4 *)ctx->c32,
                                (const TreeArgs *)ctx->trees, (const int32_t *)ctx->cb_chunk_cloud,
                                (const int32_t *)ctx->cb_chunk_first, ctx->cb_s, hp);
         } else {
             hipLaunchKernelGGL(k_tree_small<3>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(), st, c_in,
-                               (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s, hp);
+                               (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s,
+                               ctx->c_prev, ctx->drift_max, hp);
             hipLaunchKernelGGL(k_cb_pairs<3>, gb, dim3(CB_THREADS), 0, st, (const float4 *)ctx->c32,
                                (const TreeArgs *)ctx->trees, (const int32_t *)ctx->cb_chunk_cloud,
                                (const int32_t *)ctx->cb_chunk_first, ctx->cb_s, hp);
