@@ -96,8 +96,13 @@ typedef struct km_config {
                             brute path: centroids staged in LDS per tile, 64..2048,
                             0 = default (1024) */
     uint32_t flags;      /* KM_FLAG_* */
-    int64_t workspace_limit_bytes; /* 0 = unlimited; otherwise kmeans_init fails with
-                                      KM_ERR_OOM if the workspace would exceed it */
+    int64_t workspace_limit_bytes; /* 0 = unlimited.  Otherwise (the paper's m', Eq. (12)):
+                                      with leaf_size == 0 on the indexed path, f is the
+                                      smallest power of two in [8, 64] whose modelled
+                                      workspace (kmeans_workspace_bytes) fits, i.e. the
+                                      finest index the memory allows; kmeans_init fails
+                                      with KM_ERR_OOM if no f fits or if the workspace
+                                      actually allocated exceeds the limit */
 } km_config;
 
 /* Per-step counters.  A "distance evaluation" is one FP32 (or, on the FP64
@@ -129,9 +134,28 @@ typedef struct km_iter_stats {
 
 typedef struct km_ctx km_ctx;
 
-/* Device workspace kmeans_init would allocate for this configuration, in
- * bytes (an upper bound; 0 if the configuration is invalid). */
+/* Modelled device workspace of kmeans_init for this configuration, in bytes
+ * (0 if the configuration is invalid): the memory estimation of Eq. (10)-(11)
+ * adapted to this library's buffers, every buffer sized from the point,
+ * centroid, leaf, leaf-group and centroid-tree-node counts, with leaf and
+ * group counts estimated as in the paper (cells half full on average).  The
+ * leaf size is cfg->leaf_size, or the one kmeans_init would choose.
+ * kmeans_context_info reports the actual bytes next to this model. */
 EKM_API size_t kmeans_workspace_bytes(const km_config *cfg, int64_t n, int64_t k);
+
+/* What a context holds (host struct filled by kmeans_context_info). */
+typedef struct km_ctx_info {
+    int64_t device_bytes;   /* device memory the context holds (workspace and statistics rows) */
+    int64_t model_bytes;    /* kmeans_workspace_bytes' model for the context's configuration */
+    int64_t model_bytes_actual_counts; /* the same model with the actual leaf and group counts */
+    int64_t leaves, groups; /* point leaves and leaf groups of the index */
+    int64_t allocations;    /* device allocations behind device_bytes (the runtime rounds each one up
+                               to its page size, so free device memory drops by a little more) */
+    int32_t leaf_size;      /* f in use (given, chosen from the workspace limit, or tuned) */
+    int32_t leaves_per_group; /* G in use */
+} km_ctx_info;
+
+EKM_API km_status kmeans_context_info(const km_ctx *ctx, km_ctx_info *info);
 
 /* Create a context for `n` points and `k` clusters.
  *   points: device, n x d row-major, FP32 or FP64 per cfg->point_dtype.  Copied

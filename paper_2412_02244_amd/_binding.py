@@ -26,7 +26,7 @@ KM_FLAG_SMALL_LISTS = 4
 KM_FLAG_CELL_LEAVES = 8
 PHASES = ("tree", "assign", "deferred", "update")
 
-EXPORTED = ("kmeans_workspace_bytes", "kmeans_init", "kmeans_init_batched", "kmeans_step", "kmeans_run",
+EXPORTED = ("kmeans_workspace_bytes", "kmeans_context_info", "kmeans_init", "kmeans_init_batched", "kmeans_step", "kmeans_run",
             "kmeans_run_batched", "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc",
             "kmeans_last_error")
 
@@ -41,6 +41,16 @@ class KmConfig(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("point_dtype", ctypes.c_int32), ("algo", ctypes.c_int32),
                 ("leaf_size", ctypes.c_int32), ("cand_tile", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("workspace_limit_bytes", ctypes.c_int64)]
+
+
+class KmCtxInfo(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_int64), ("model_bytes", ctypes.c_int64),
+                ("model_bytes_actual_counts", ctypes.c_int64), ("leaves", ctypes.c_int64),
+                ("groups", ctypes.c_int64), ("allocations", ctypes.c_int64), ("leaf_size", ctypes.c_int32),
+                ("leaves_per_group", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class KmIterStats(ctypes.Structure):
@@ -69,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.kmeans_workspace_bytes.argtypes = [ctypes.POINTER(KmConfig), I64, I64]
     lib.kmeans_workspace_bytes.restype = ctypes.c_size_t
+    lib.kmeans_context_info.argtypes = [P, ctypes.POINTER(KmCtxInfo)]
     lib.kmeans_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KmConfig), P, I64, I64, P]
     lib.kmeans_init_batched.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KmConfig), P, ctypes.POINTER(I64),
                                         ctypes.POINTER(I64), I32, P]
@@ -83,7 +94,7 @@ def load_library(path: str = LIB_PATH):
     lib.distortion_bwd.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.distortion_bwd_noalloc.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.kmeans_last_error.restype = ctypes.c_char_p
-    for name in ("kmeans_init", "kmeans_init_batched", "kmeans_run_batched", "kmeans_step", "kmeans_run",
+    for name in ("kmeans_context_info", "kmeans_init", "kmeans_init_batched", "kmeans_run_batched", "kmeans_step", "kmeans_run",
                  "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd",
                  "distortion_bwd_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
@@ -123,9 +134,18 @@ def _pt_dtype(t: torch.Tensor) -> int:
 
 
 def kmeans_workspace_bytes(n: int, k: int, d: int, point_dtype: int = KM_F32, algo: int = KM_INDEXED,
-                           leaf_size: int = 0, cand_tile: int = 0) -> int:
-    cfg = KmConfig(d, point_dtype, algo, leaf_size, cand_tile, 0, 0)
+                           leaf_size: int = 0, cand_tile: int = 0, flags: int = 0,
+                           workspace_limit_bytes: int = 0) -> int:
+    """Modelled device workspace of kmeans_init (0 for an invalid configuration)."""
+    cfg = KmConfig(d, point_dtype, algo, leaf_size, cand_tile, flags, workspace_limit_bytes)
     return int(load_library().kmeans_workspace_bytes(ctypes.byref(cfg), n, k))
+
+
+def kmeans_context_info(ctx: "Context") -> dict:
+    """Device bytes held, the model's prediction, leaf size and counts of a context."""
+    info = KmCtxInfo()
+    _check(load_library().kmeans_context_info(ctypes.c_void_p(ctx.handle), ctypes.byref(info)))
+    return info.as_dict()
 
 
 class Context:

@@ -85,34 +85,135 @@ static km_status check_config(const km_config *cfg, int64_t n, int64_t k)
     return KM_OK;
 }
 
-// Upper bound of the device workspace (leaves bounded by n).
-static size_t workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
+// ------------------------------------------------------------ memory model
+// The device workspace of a context, buffer by buffer, from the counts that
+// size them (the memory estimation of Eq. (10)-(11), adapted to this
+// library's buffers): per point, per leaf, per leaf group, per centroid and
+// per centroid-tree node.  ws_bytes is exact for given counts; the counts of
+// leaves and groups are only known once the points are sorted, so the
+// estimate takes cells half full on average, the paper's assumption: a
+// group cell (at most G f points) holds G f / 2 points, cut into leaves of
+// f points (default leaves), or a leaf cell (at most f points) holds f / 2
+// points (KM_FLAG_CELL_LEAVES, and the leaf cuts of the brute path).
+struct WsCounts {
+    int64_t n = 0, k = 0, B = 1;
+    int64_t L = 0, groups = 0;  // leaves, leaf groups
+    int64_t nodes = 0, cb_chunks = 0; // centroid-tree nodes and inter-bound chunks over all clouds
+};
+
+// The workspace in the order the build allocates it: `build` (cloud tables,
+// sort keys and scratch, kept for the centroid sort, and the SoA points:
+// known from n alone), `rest` (leaves, per-step buffers, centroid trees and
+// per-leaf state: needs the leaf count), `groups` (leaf groups and their
+// statistics rows: needs the group count) and the statistics rows of a run.
+struct WsParts {
+    size_t build = 0, rest = 0, groups = 0, hist = 0;
+    size_t total() const { return build + rest + groups + hist; }
+};
+
+static WsParts ws_parts(const km_config *cfg, const WsCounts &c)
 {
+    auto al = [](int64_t count, size_t elem) { return alloc_size((size_t)(count > 0 ? count : 0), elem); };
     const int d = cfg->d;
     const size_t es = cfg->point_dtype == KM_F32 ? 4 : 8;
-    size_t b = 0;
-    b += (size_t)n * d * es;              // xs
-    b += (size_t)n * 4 * 5;               // perm, a, keys, keys2, vals2
-    b += radix_scratch_words(n) * 4;      // histogram
-    b += scan_scratch_words(radix_scratch_words(n) > (size_t)n ? radix_scratch_words(n) : n) * 4;
-    int64_t L = n;                        // leaves <= n
-    b += (size_t)(L + 1) * 4;             // leaf_start
-    if (cfg->algo == KM_INDEXED) {
-        b += (size_t)L * (32 + d * 16 + 4 + 4 + 4) + 4; // leaf box, exact sums, previous cluster, distance
-                                                         // bound, deferred list
-        b += (size_t)L * 36 + 4;                      // groups (at most one per leaf): boxes, first leaves
+    const bool indexed = cfg->algo == KM_INDEXED;
+    const bool leaf_state = indexed && cfg->point_dtype == KM_F32;
+    const int64_t n = c.n, k = c.k, L = c.L;
+    const int64_t hist = (int64_t)radix_scratch_words(n);
+    WsParts p;
+    p.build = 2 * al(c.B + 1, 8) + al(c.B + 1, scan_record_bytes()) + al(c.B, sizeof(Grid)) + 4 * al(n, 4) +
+              al(hist, 4) + al((int64_t)scan_scratch_words(hist > n ? hist : n), 4) + al(n * d, es);
+    p.rest = al(L + 1, 4);
+    if (leaf_state)
+        p.rest += al(2 * L, 16) + al(L * d * 2, 8) + al(L, 4);
+    p.rest += al(n, 4) + al(k, 16) + al(k, 4) + al(1, 4) + al(k * d * 2, 8) + al(k, 4);
+    p.rest += al(sse_blocks(n), 8) + al(NSTAT, 8) + al(1, 8) + al(k * d, 8);
+    if (indexed) // centroid trees, inter bounds, per-leaf state
+        p.rest += al(k, 16) + 2 * al(c.nodes, 16) + al(c.B, sizeof(TreeArgs)) + 2 * al(c.cb_chunks, 4) +
+                  3 * al(L, 4) + al(1, 4) + 3 * al(k, 4) + al(1, 4) + al(k * d, 8);
+    p.rest += al(CTL_N, 4);
+    const int64_t nblk = indexed ? (c.groups + 3) / 4 + HEAVY_BLOCKS : (n + 255) / 256;
+    if (leaf_state)
+        p.groups = al(c.groups + 1, 4) + al(2 * c.groups, 16) + al(c.groups, 4);
+    p.groups += al(nblk * NSTAT, 8);
+    p.hist = (size_t)HIST_ROWS * (NSTAT + 1) * 8;
+    return p;
+}
+
+static size_t ws_bytes(const km_config *cfg, const WsCounts &c) { return ws_parts(cfg, c).total(); }
+
+// Estimated counts for B clouds (pt_off / c_off, host) at leaf size f and G
+// leaves per group.
+static WsCounts ws_estimate(const km_config *cfg, int B, const int64_t *pt_off, const int64_t *c_off, int f, int G)
+{
+    WsCounts c;
+    c.n = pt_off[B];
+    c.k = c_off[B];
+    c.B = B;
+    const bool packed =
+        cfg->algo == KM_INDEXED && cfg->point_dtype == KM_F32 && !(cfg->flags & KM_FLAG_CELL_LEAVES);
+    for (int b = 0; b < B; ++b) {
+        const int64_t nb = pt_off[b + 1] - pt_off[b], kb = c_off[b + 1] - c_off[b];
+        if (packed) {
+            const int64_t cells = (2 * nb + (int64_t)G * f - 1) / ((int64_t)G * f); // half-full group cells
+            c.groups += cells;
+            c.L += cells * (((int64_t)G * f / 2 + f - 1) / f);
+        } else {
+            const int64_t leaves = (2 * nb + f - 1) / f; // half-full leaf cells
+            c.L += leaves;
+            c.groups += (leaves + G - 1) / G;
+        }
         TreeArgs T;
-        tree_layout(k, T);
-        b += (size_t)T.nnodes * 32 + (size_t)k * 16;  // node boxes, tree-ordered centroids
+        tree_layout(kb, T);
+        c.nodes += T.nnodes;
+        c.cb_chunks += (kb + WAVE - 1) / WAVE;
     }
-    b += (size_t)k * (16 + 4 + d * 16 + 4 + d * 8); // c32, cval, acc, cnt, kmeans_run's centroids
-    b += (size_t)HIST_ROWS * (NSTAT + 1) * 8;        // per-step statistics rows of a run
-    int64_t nblk = cfg->algo == KM_INDEXED ? L + HEAVY_BLOCKS : (n + 255) / 256; // statistics rows
-    b += (size_t)nblk * NSTAT * 8 + (size_t)sse_blocks(n) * 8;
-    if (cfg->algo == KM_INDEXED)
-        b += (size_t)k * (4 + 4 + 4 + 8 * d) + 4; // inter bounds, drift, previous centroids
-    b += 4096;
-    return b;
+    return c;
+}
+
+static size_t model_bytes(const km_config *cfg, int B, const int64_t *pt_off, const int64_t *c_off, int f, int G)
+{
+    return ws_bytes(cfg, ws_estimate(cfg, B, pt_off, c_off, f, G));
+}
+
+size_t ctx_bytes_after_counts(const km_ctx *ctx, int64_t L, int64_t groups, bool with_groups)
+{
+    WsCounts c = ws_estimate(&ctx->cfg, ctx->B, ctx->h_pt_off.data(), ctx->h_c_off.data(), ctx->f, ctx->G);
+    c.L = L;
+    c.groups = groups;
+    const WsParts p = ws_parts(&ctx->cfg, c);
+    return p.rest + (with_groups ? p.groups : 0);
+}
+
+// Device bytes a context holds.
+static size_t ctx_device_bytes(const km_ctx *ctx)
+{
+    return ctx->mem.bytes + (size_t)ctx->hist_cap * (NSTAT + 1) * sizeof(int64_t);
+}
+
+// Leaves per group for a configuration (cand_tile, else the default).
+static int default_groups(const km_config *cfg)
+{
+    if (cfg->algo == KM_INDEXED && cfg->cand_tile)
+        return cfg->cand_tile;
+    return cfg->d == 2 && !(cfg->flags & KM_FLAG_CELL_LEAVES) ? DEFAULT_G_2D : GROUP_LEAVES;
+}
+
+// Leaf size: cfg->leaf_size, or with a workspace limit on the indexed path
+// the smallest power of two in [8, 64] whose modelled workspace fits (the
+// memory-tunable index of Eq. (12): the finest index the memory allows), or
+// 64 (0 if nothing fits).
+static int choose_leaf_size(const km_config *cfg, int B, const int64_t *pt_off, const int64_t *c_off)
+{
+    if (cfg->leaf_size)
+        return cfg->leaf_size;
+    if (cfg->algo != KM_INDEXED || cfg->workspace_limit_bytes <= 0)
+        return 64;
+    const int G = default_groups(cfg);
+    for (int f = 8; f <= MAX_LEAF; f *= 2)
+        if (model_bytes(cfg, B, pt_off, c_off, f, G) <= (size_t)cfg->workspace_limit_bytes)
+            return f;
+    return 0;
 }
 
 static km_status alloc_fail(km_ctx *ctx)
@@ -253,7 +354,29 @@ size_t kmeans_workspace_bytes(const km_config *cfg, int64_t n, int64_t k)
 {
     if (check_config(cfg, n, k) != KM_OK)
         return 0;
-    return workspace_bytes(cfg, n, k);
+    const int64_t pt_off[2] = {0, n}, c_off[2] = {0, k};
+    const int f = choose_leaf_size(cfg, 1, pt_off, c_off);
+    return model_bytes(cfg, 1, pt_off, c_off, f ? f : MAX_LEAF, default_groups(cfg));
+}
+
+km_status kmeans_context_info(const km_ctx *ctx, km_ctx_info *info)
+{
+    if (!ctx || !info) {
+        set_error("kmeans_context_info: null argument");
+        return KM_ERR_INVALID;
+    }
+    info->device_bytes = (int64_t)ctx_device_bytes(ctx);
+    info->leaf_size = ctx->f;
+    info->leaves_per_group = ctx->G;
+    info->leaves = ctx->L;
+    info->groups = ctx->ngroups;
+    info->allocations = (int64_t)ctx->mem.ptrs.size() + (ctx->stat_hist ? 1 : 0);
+    WsCounts c = ws_estimate(&ctx->cfg, ctx->B, ctx->h_pt_off.data(), ctx->h_c_off.data(), ctx->f, ctx->G);
+    info->model_bytes = (int64_t)ws_bytes(&ctx->cfg, c);
+    c.L = ctx->L;
+    c.groups = ctx->ngroups;
+    info->model_bytes_actual_counts = (int64_t)ws_bytes(&ctx->cfg, c);
+    return KM_OK;
 }
 
 const char *kmeans_last_error(void) { return g_error.c_str(); }
@@ -353,12 +476,16 @@ km_status kmeans_destroy(km_ctx *ctx)
 // Context over B clouds (B = 1: kmeans_init) with point / centroid offsets
 // pt_off / c_off ([B + 1], host), already validated.
 static km_status init_context(km_ctx **out, const km_config *cfg, const void *points, int B, const int64_t *pt_off,
-                              const int64_t *c_off, void *stream, bool capture_chunk = true)
+                              const int64_t *c_off, void *stream, bool capture_chunk = true, int f_retry = 0)
 {
     const int64_t n = pt_off[B], k = c_off[B];
-    if (cfg->workspace_limit_bytes > 0 && workspace_bytes(cfg, n, k) > (size_t)cfg->workspace_limit_bytes) {
-        set_error("kmeans_init: workspace of " + std::to_string(workspace_bytes(cfg, n, k)) +
-                  " bytes exceeds workspace_limit_bytes");
+    const int f = f_retry ? f_retry : choose_leaf_size(cfg, B, pt_off, c_off);
+    const int G = default_groups(cfg);
+    if (cfg->workspace_limit_bytes > 0 &&
+        (f == 0 || model_bytes(cfg, B, pt_off, c_off, f, G) > (size_t)cfg->workspace_limit_bytes)) {
+        set_error("kmeans_init: the modelled workspace (" +
+                  std::to_string(model_bytes(cfg, B, pt_off, c_off, f ? f : MAX_LEAF, G)) +
+                  " bytes at the largest leaf size) exceeds workspace_limit_bytes");
         return KM_ERR_OOM;
     }
     static std::once_flag once;
@@ -372,10 +499,8 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     ctx->n = n;
     ctx->k = k;
     ctx->d = cfg->d;
-    ctx->f = cfg->leaf_size ? cfg->leaf_size : 64;
-    ctx->G = cfg->algo == KM_INDEXED && cfg->cand_tile
-                 ? cfg->cand_tile
-                 : (cfg->d == 2 && !(cfg->flags & KM_FLAG_CELL_LEAVES) ? DEFAULT_G_2D : GROUP_LEAVES);
+    ctx->f = f;
+    ctx->G = G;
     ctx->tile = cfg->algo == KM_BRUTE && cfg->cand_tile ? cfg->cand_tile : 1024;
     ctx->stream = (hipStream_t)stream;
     ctx->small_lists = (cfg->flags & KM_FLAG_SMALL_LISTS) ? 1 : 0;
@@ -385,6 +510,11 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     ctx->B = B;
     ctx->h_pt_off.assign(pt_off, pt_off + B + 1);
     ctx->h_c_off.assign(c_off, c_off + B + 1);
+    // the buffers of the index build, in one allocation (their sizes follow from n)
+    if (!ctx_arena(ctx, ws_parts(cfg, ws_estimate(cfg, B, pt_off, c_off, f, G)).build)) {
+        kmeans_destroy(ctx);
+        return alloc_fail(nullptr);
+    }
     ctx->pt_off = ctx_alloc<int64_t>(ctx, B + 1);
     ctx->c_off = ctx_alloc<int64_t>(ctx, B + 1);
     if (!ctx->pt_off || !ctx->c_off) {
@@ -532,9 +662,11 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     // (a context that records phase times launches its steps one by one)
     if (capture_chunk && !(cfg->flags & KM_FLAG_TIMING))
         (void)chunk_graph(ctx, ctx->c_run);
-    if (cfg->workspace_limit_bytes > 0 && ctx->mem.bytes > (size_t)cfg->workspace_limit_bytes) {
-        size_t used = ctx->mem.bytes;
+    if (cfg->workspace_limit_bytes > 0 && ctx_device_bytes(ctx) > (size_t)cfg->workspace_limit_bytes) {
+        const size_t used = ctx_device_bytes(ctx);
         kmeans_destroy(ctx);
+        if (!cfg->leaf_size && f < MAX_LEAF) // the model's estimate was short: the next coarser index
+            return init_context(out, cfg, points, B, pt_off, c_off, stream, capture_chunk, 2 * f);
         set_error("kmeans_init: workspace of " + std::to_string(used) + " bytes exceeds workspace_limit_bytes");
         return KM_ERR_OOM;
     }
@@ -827,7 +959,8 @@ static km_status autotune(const km_config *cfg, const void *points, const int64_
                             std::to_string(lg((double)pt_offs[B] / B)) + "/k" +
                             std::to_string(lg((double)c_offs[B] / B)) + "/f" + std::to_string(cfg->leaf_size) +
                             "/t" + std::to_string(cfg->cand_tile) +
-                            ((cfg->flags & KM_FLAG_CELL_LEAVES) ? "/cells" : "");
+                            ((cfg->flags & KM_FLAG_CELL_LEAVES) ? "/cells" : "") + "/m" +
+                            std::to_string(cfg->workspace_limit_bytes);
     {
         std::lock_guard<std::mutex> lock(mu);
         auto it = cache.find(key);
@@ -873,9 +1006,17 @@ static km_status autotune(const km_config *cfg, const void *points, const int64_
             s = KM_ERR_HIP;
     }
     float best = INFINITY;
+    bool any = false;
     for (size_t a = 0; s == KM_OK && a < fs.size(); ++a)
         for (size_t g = 0; s == KM_OK && g < Gs.size(); ++g) {
             km_config c2 = *cfg;
+            if (cfg->workspace_limit_bytes > 0) { // only candidates whose full-size workspace fits
+                c2.leaf_size = fs[a];
+                c2.cand_tile = Gs[g];
+                if (model_bytes(&c2, B, pt_offs, c_offs, fs[a], Gs[g]) > (size_t)cfg->workspace_limit_bytes)
+                    continue;
+            }
+            any = true;
             c2.leaf_size = fs[a];
             c2.cand_tile = Gs[g];
             c2.flags &= ~(KM_FLAG_TIMING | KM_FLAG_SSE | KM_FLAG_SMALL_LISTS);
@@ -900,6 +1041,10 @@ static km_status autotune(const km_config *cfg, const void *points, const int64_
                 G_out = Gs[g];
             }
         }
+    if (s == KM_OK && !any) {
+        set_error("kmeans_run_batched: no leaf size / list length fits workspace_limit_bytes");
+        s = KM_ERR_OOM;
+    }
     if (e0)
         hipEventDestroy(e0);
     if (e1)

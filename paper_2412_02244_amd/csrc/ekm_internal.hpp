@@ -621,6 +621,8 @@ struct km_ctx {
     int64_t rs_hist_len = 0;
     uint32_t *scan_tmp = nullptr;
     ekm::Scratch mem;
+    char *arena = nullptr; // current arena (see ctx_alloc)
+    size_t arena_size = 0, arena_used = 0;
     int steps_done = 0;
     int32_t *ctl = nullptr;       // [CTL_N] device-side loop control
     int32_t *host_ctl = nullptr;  // pinned [(RUN_AHEAD + 1) * CTL_N]: ctl copies taken after launch groups
@@ -646,18 +648,51 @@ void set_error(const std::string &msg);
 bool hip_ok(hipError_t e, const char *what);
 
 // Device allocation tracked in the context.
+// Device memory of a context: buffers are carved, ALLOC_ALIGN-aligned, from
+// the current arena (one hipMalloc sized for a phase of the build) while it
+// has room, else allocated on their own.  mem.bytes counts what the context
+// took from the runtime.
+constexpr size_t ALLOC_ALIGN = 256;
+inline size_t alloc_size(size_t count, size_t elem)
+{
+    const size_t b = (count ? count : 1) * elem;
+    return (b + ALLOC_ALIGN - 1) / ALLOC_ALIGN * ALLOC_ALIGN;
+}
+
 template <class T>
 T *ctx_alloc(km_ctx *ctx, size_t count)
 {
+    const size_t bytes = alloc_size(count, sizeof(T));
+    if (ctx->arena && ctx->arena_used + bytes <= ctx->arena_size) {
+        void *p = ctx->arena + ctx->arena_used;
+        ctx->arena_used += bytes;
+        return (T *)p;
+    }
     void *p = nullptr;
-    if (count == 0)
-        count = 1;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess)
+    if (hipMalloc(&p, bytes) != hipSuccess)
         return nullptr;
     ctx->mem.ptrs.push_back(p);
-    ctx->mem.bytes += count * sizeof(T);
+    ctx->mem.bytes += bytes;
     return (T *)p;
 }
+
+// Starts a new arena of `bytes` (the rest of the previous one is unused).
+inline bool ctx_arena(km_ctx *ctx, size_t bytes)
+{
+    void *p = nullptr;
+    if (bytes == 0 || hipMalloc(&p, bytes) != hipSuccess)
+        return false;
+    ctx->mem.ptrs.push_back(p);
+    ctx->mem.bytes += bytes;
+    ctx->arena = (char *)p;
+    ctx->arena_size = bytes;
+    ctx->arena_used = 0;
+    return true;
+}
+
+// Bytes of the buffers the build allocates once the leaf count L (and, with
+// `with_groups`, the group count) is known (api.hip, from the workspace model).
+size_t ctx_bytes_after_counts(const km_ctx *ctx, int64_t L, int64_t groups, bool with_groups);
 
 // sort.hip
 size_t radix_scratch_words(int64_t n);
@@ -667,6 +702,7 @@ hipError_t exclusive_scan_u32(uint32_t *data, int64_t n, uint32_t *tmp, hipStrea
 size_t scan_scratch_words(int64_t n);
 
 // leaves.hip
+size_t scan_record_bytes(); // input-scan record per cloud (leaves.hip)
 km_status build_leaves(km_ctx *ctx, const void *points);
 
 // tree.hip

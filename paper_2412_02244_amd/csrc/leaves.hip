@@ -580,6 +580,12 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         return KM_ERR_HIP;
     int64_t L = (int64_t)last[0] + last[1];
     ctx->L = L;
+    // the rest of the workspace in one allocation, now that its sizes are
+    // known (the leaf groups too with default leaves)
+    if (!ctx_arena(ctx, ctx_bytes_after_counts(ctx, L, ncells, packed))) {
+        set_error("kmeans_init: device allocation failed");
+        return KM_ERR_OOM;
+    }
     ctx->leaf_start = ctx_alloc<int32_t>(ctx, L + 1);
     if (!ctx->leaf_start) {
         set_error("kmeans_init: device allocation failed");
@@ -684,6 +690,8 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         return KM_ERR_HIP;
     return KM_OK;
 }
+
+size_t scan_record_bytes() { return sizeof(ScanOut); }
 
 km_status build_leaves(km_ctx *ctx, const void *points)
 {

@@ -120,3 +120,28 @@ def test_workspace_bytes_model(lib):
     assert 0 < brute < big
     # at least the points, the permutation and the assignment
     assert big >= 1_000_000 * (2 * 4 + 4 + 4)
+
+
+def test_memory_model_and_leaf_size_from_budget(lib):
+    """Eq. (10)-(12) on this library's buffers: the modelled workspace grows
+    as the leaves shrink, and with a budget (and leaf_size 0) the leaf size is
+    the smallest whose modelled workspace fits."""
+    import paper_2412_02244_amd as ekm
+    n, k = 1_000_000, 1000
+    m = {f: ekm.kmeans_workspace_bytes(n, k, 2, leaf_size=f) for f in (8, 16, 32, 64)}
+    assert m[8] > m[16] > m[32] > m[64] > 0
+    # the difference between two leaf sizes is the per-leaf state of the extra leaves
+    assert m[8] - m[64] > (n // 8 - n // 64) * 32
+    assert ekm.kmeans_workspace_bytes(n, k, 2) == m[64]  # no budget: the default leaf size
+    for f in (8, 16, 32, 64):
+        assert ekm.kmeans_workspace_bytes(n, k, 2, workspace_limit_bytes=m[f]) == m[f]
+        if f > 8:
+            assert ekm.kmeans_workspace_bytes(n, k, 2, workspace_limit_bytes=m[f // 2] - 1) == m[f]
+    # twice the points: about twice the workspace (points dominate)
+    m2 = ekm.kmeans_workspace_bytes(2 * n, k, 2, leaf_size=64)
+    assert 1.9 < m2 / m[64] < 2.1
+    # a budget below the coarsest index is rejected before any GPU work
+    cfg = _cfg(ekm, workspace_limit_bytes=m[64] - 1)
+    h = ctypes.c_void_p()
+    assert lib.kmeans_init(ctypes.byref(h), ctypes.byref(cfg), ctypes.c_void_p(16), n, k, None) == ekm.KM_ERR_OOM
+    assert "workspace" in ekm.kmeans_last_error()
