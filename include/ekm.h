@@ -157,6 +157,52 @@ typedef struct km_ctx_info {
 
 EKM_API km_status kmeans_context_info(const km_ctx *ctx, km_ctx_info *info);
 
+/* ------------------------------------------------------------------------
+ * Runtime prediction (the subsection on runtime prediction, Eq. (13)-(21)):
+ * an iteration-number regressor, a per-iteration runtime regressor with
+ * interaction terms, trained on measured runs, and an online adjustment by
+ * a Gaussian process with an asymmetric kernel.  Host memory and host
+ * computation only; not thread safe per predictor.
+ *
+ * A workload is described by nfeat meta-features (for instance those of
+ * kmeans_context_features).  The per-iteration regressor's base features
+ * are the meta-features and 1 / j for iteration j; its terms are every
+ * product of at most `order` distinct base features and an intercept. */
+typedef struct km_predictor km_predictor;
+
+/* q: largest iteration number; sigma: kernel width in iterations; noise:
+ * observation noise of the adjustment.  KM_ERR_INVALID unless q >= 1,
+ * 0 <= nfeat <= 16, order >= 1, sigma > 0, noise >= 0. */
+EKM_API km_status kmeans_predictor_create(km_predictor **out, int32_t q, int32_t nfeat, int32_t order,
+                                          double sigma, double noise);
+EKM_API km_status kmeans_predictor_destroy(km_predictor *p);
+/* A training run: its meta-features (host, nfeat) and the measured times of
+ * its iterations 1..iters (host, ms; 1 <= iters <= q). */
+EKM_API km_status kmeans_predictor_add_run(km_predictor *p, const double *feat, const double *iter_ms,
+                                           int32_t iters);
+/* Least-squares fit of both regressors over the runs added so far (Eq. (17),
+ * with a small ridge term; every measured iteration is a row of the
+ * runtime regressor). */
+EKM_API km_status kmeans_predictor_fit(km_predictor *p);
+/* Predicted iteration number, per-iteration times (host, q values, or NULL)
+ * and total time (the sum over the predicted iterations) of a workload. */
+EKM_API km_status kmeans_predictor_predict(const km_predictor *p, const double *feat, int32_t *iters_out,
+                                           double *iter_ms, double *total_ms);
+/* Starts monitoring a task with these meta-features (forgets earlier
+ * observations). */
+EKM_API km_status kmeans_predictor_begin(km_predictor *p, const double *feat);
+/* Iteration `iter` of the monitored task took `ms`: updates the adjustment
+ * (g = predicted / measured, prior mean 1, asymmetric kernel) and returns
+ * the remaining time up to the predicted iteration number and the total
+ * (measured so far + remaining).  Iterations must be reported in increasing
+ * order. */
+EKM_API km_status kmeans_predictor_observe(km_predictor *p, int32_t iter, double ms, double *remaining_ms,
+                                           double *total_ms);
+/* Meta-features of a context: ln n, ln k, d, ln f, ln(points per leaf),
+ * ln(leaves), ln(leaf groups), centroid-tree levels; writes min(cap, 8)
+ * values and sets *nfeat = 8. */
+EKM_API km_status kmeans_context_features(const km_ctx *ctx, double *feat, int32_t cap, int32_t *nfeat);
+
 /* Create a context for `n` points and `k` clusters.
  *   points: device, n x d row-major, FP32 or FP64 per cfg->point_dtype.  Copied
  *           into the context (reordered along a Morton curve and cut into

@@ -26,7 +26,9 @@ KM_FLAG_SMALL_LISTS = 4
 KM_FLAG_CELL_LEAVES = 8
 PHASES = ("tree", "assign", "deferred", "update")
 
-EXPORTED = ("kmeans_workspace_bytes", "kmeans_context_info", "kmeans_init", "kmeans_init_batched", "kmeans_step", "kmeans_run",
+EXPORTED = ("kmeans_workspace_bytes", "kmeans_context_info", "kmeans_context_features", "kmeans_predictor_create",
+            "kmeans_predictor_destroy", "kmeans_predictor_add_run", "kmeans_predictor_fit",
+            "kmeans_predictor_predict", "kmeans_predictor_begin", "kmeans_predictor_observe", "kmeans_init", "kmeans_init_batched", "kmeans_step", "kmeans_run",
             "kmeans_run_batched", "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd", "distortion_bwd_noalloc",
             "kmeans_last_error")
 
@@ -80,6 +82,15 @@ def load_library(path: str = LIB_PATH):
     lib.kmeans_workspace_bytes.argtypes = [ctypes.POINTER(KmConfig), I64, I64]
     lib.kmeans_workspace_bytes.restype = ctypes.c_size_t
     lib.kmeans_context_info.argtypes = [P, ctypes.POINTER(KmCtxInfo)]
+    D, DP = ctypes.c_double, ctypes.POINTER(ctypes.c_double)
+    lib.kmeans_context_features.argtypes = [P, DP, I32, ctypes.POINTER(I32)]
+    lib.kmeans_predictor_create.argtypes = [ctypes.POINTER(P), I32, I32, I32, D, D]
+    lib.kmeans_predictor_destroy.argtypes = [P]
+    lib.kmeans_predictor_add_run.argtypes = [P, DP, DP, I32]
+    lib.kmeans_predictor_fit.argtypes = [P]
+    lib.kmeans_predictor_predict.argtypes = [P, DP, ctypes.POINTER(I32), DP, DP]
+    lib.kmeans_predictor_begin.argtypes = [P, DP]
+    lib.kmeans_predictor_observe.argtypes = [P, I32, D, DP, DP]
     lib.kmeans_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KmConfig), P, I64, I64, P]
     lib.kmeans_init_batched.argtypes = [ctypes.POINTER(P), ctypes.POINTER(KmConfig), P, ctypes.POINTER(I64),
                                         ctypes.POINTER(I64), I32, P]
@@ -94,7 +105,9 @@ def load_library(path: str = LIB_PATH):
     lib.distortion_bwd.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.distortion_bwd_noalloc.argtypes = [P, P, P, P, I32, I64, I64, I64, I32, P, P, P]
     lib.kmeans_last_error.restype = ctypes.c_char_p
-    for name in ("kmeans_context_info", "kmeans_init", "kmeans_init_batched", "kmeans_run_batched", "kmeans_step", "kmeans_run",
+    for name in ("kmeans_context_info", "kmeans_context_features", "kmeans_predictor_create",
+                 "kmeans_predictor_destroy", "kmeans_predictor_add_run", "kmeans_predictor_fit",
+                 "kmeans_predictor_predict", "kmeans_predictor_begin", "kmeans_predictor_observe", "kmeans_init", "kmeans_init_batched", "kmeans_run_batched", "kmeans_step", "kmeans_run",
                  "kmeans_destroy", "kmeans_phase_times", "kmeans_step_times", "distortion_fwd", "distortion_bwd",
                  "distortion_bwd_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
@@ -224,6 +237,68 @@ def kmeans_run_batched(points: torch.Tensor, pt_offs, c_inout: torch.Tensor, c_o
         None if assign_out is None else _dev(assign_out, "assign_out", torch.int32), B, ctypes.byref(cfg), iters,
         _stream(), tuned))
     return tuned[0], tuned[1]
+
+
+def kmeans_context_features(ctx: Context) -> list:
+    """Meta-features of a context: ln n, ln k, d, ln f, ln(points per leaf), ln(leaves), ln(groups),
+    centroid-tree levels."""
+    buf = (ctypes.c_double * 16)()
+    nf = ctypes.c_int32(0)
+    _check(load_library().kmeans_context_features(ctypes.c_void_p(ctx.handle), buf, 16, ctypes.byref(nf)))
+    return [buf[i] for i in range(nf.value)]
+
+
+def _dvec(v):
+    v = [float(x) for x in v]
+    return (ctypes.c_double * max(1, len(v)))(*v)
+
+
+class Predictor:
+    """Runtime predictor (iteration-number regressor, per-iteration polynomial regressor,
+    asymmetric-kernel GP adjustment); host-side, in the library."""
+
+    def __init__(self, q: int, nfeat: int, order: int = 2, sigma: float = 2.0, noise: float = 1e-2):
+        self.q, self.nfeat = q, nfeat
+        h = ctypes.c_void_p()
+        _check(load_library().kmeans_predictor_create(ctypes.byref(h), q, nfeat, order, sigma, noise))
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            load_library().kmeans_predictor_destroy(ctypes.c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_run(self, feat, iter_ms):
+        _check(load_library().kmeans_predictor_add_run(ctypes.c_void_p(self.handle), _dvec(feat), _dvec(iter_ms),
+                                                       len(iter_ms)))
+
+    def fit(self):
+        _check(load_library().kmeans_predictor_fit(ctypes.c_void_p(self.handle)))
+
+    def predict(self, feat):
+        """-> (iterations, per-iteration ms [q], total ms)"""
+        it = ctypes.c_int32(0)
+        per = (ctypes.c_double * self.q)()
+        tot = ctypes.c_double(0.0)
+        _check(load_library().kmeans_predictor_predict(ctypes.c_void_p(self.handle), _dvec(feat), ctypes.byref(it),
+                                                       per, ctypes.byref(tot)))
+        return it.value, list(per), tot.value
+
+    def begin(self, feat):
+        _check(load_library().kmeans_predictor_begin(ctypes.c_void_p(self.handle), _dvec(feat)))
+
+    def observe(self, iteration: int, ms: float):
+        """-> (remaining ms, total ms)"""
+        rem, tot = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(load_library().kmeans_predictor_observe(ctypes.c_void_p(self.handle), iteration, ms,
+                                                       ctypes.byref(rem), ctypes.byref(tot)))
+        return rem.value, tot.value
 
 
 def kmeans_step(ctx: Context, c_in: torch.Tensor, c_out: torch.Tensor | None = None,

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libekm.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "sort.hip", "leaves.hip", "tree.hip", "assign.hip", "reduce.hip", "distortion.hip"]
+SOURCES = ["api.hip", "sort.hip", "leaves.hip", "tree.hip", "assign.hip", "reduce.hip", "distortion.hip",
+           "predict.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
