@@ -130,6 +130,9 @@ typedef struct km_iter_stats {
     int64_t group_overflows;    /* leaf groups whose shared candidate list did not fit */
     int64_t groups_skipped;     /* leaf groups with every leaf kept by the inter bound (no
                                    centroid-tree descent) */
+    int64_t region_points;      /* points of leaf groups (regions: a compact Morton cell of at
+                                   most G leaves) whose candidate list held a single centroid:
+                                   the region is assigned as a unit */
 } km_iter_stats;
 
 typedef struct km_ctx km_ctx;

@@ -61,7 +61,8 @@ class KmIterStats(ctypes.Structure):
                 ("cand_total", ctypes.c_int64), ("leaves", ctypes.c_int64), ("sse", ctypes.c_double),
                 ("inter_leaf_points", ctypes.c_int64), ("inter_points", ctypes.c_int64),
                 ("fallback_points", ctypes.c_int64), ("deferred_leaves", ctypes.c_int64),
-                ("group_overflows", ctypes.c_int64), ("groups_skipped", ctypes.c_int64)]
+                ("group_overflows", ctypes.c_int64), ("groups_skipped", ctypes.c_int64),
+                ("region_points", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -242,6 +242,7 @@ static void fill_stats(const km_ctx *ctx, const int64_t *h, km_iter_stats *stats
     stats->deferred_leaves = h[ST_DEFERRED];
     stats->group_overflows = h[ST_GROUP_OVF];
     stats->groups_skipped = h[ST_GROUP_SKIP];
+    stats->region_points = h[ST_REGION_PTS];
 }
 
 // One step's launches: A1 tree (+ inter bounds), A2-A5 assignment passes,

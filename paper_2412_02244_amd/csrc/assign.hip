@@ -844,7 +844,10 @@ __device__ inline void defer_leaf(const AssignArgs &A, int64_t l, int32_t (&st)[
 
 // k_assign_waves: one wave per group (at most GROUP_LEAVES consecutive
 // leaves inside one compact Morton cell, see leaves.hip); the waves of a
-// workgroup are independent and the kernel has no workgroup barrier.
+// workgroup are independent and the kernel has no workgroup barrier.  The
+// points form a three-level hierarchy, region (the group's cell) -> leaf ->
+// point, and the region's candidate list and bounds pass down to its leaves
+// (Eq. (7)).
 //
 //  1. Inter bound (Eq. (5)): a leaf wholly in cluster j whose box lies
 //     within half of cb_j (the distance from c_j to its nearest other
@@ -858,7 +861,8 @@ __device__ inline void defer_leaf(const AssignArgs &A, int64_t l, int32_t (&st)[
 //     a centroid outside S has min-distance to b at least its min-distance
 //     to the searched box, above prune_threshold(U_box) >=
 //     prune_threshold(U_b), and the centroid that realised U_box is in S.
-//  4. A leaf with one candidate is assigned to it without any distance
+//  4. A region whose list holds one centroid is assigned to it whole, and a
+//     leaf with one candidate is assigned to it, without any distance
 //     evaluation (Eq. (6)'s batch assignment).  Otherwise each lane (one
 //     point) keeps its cluster by the inter bound (Eq. (4)) or scans the
 //     candidates in FP32; a point whose best-vs-second margin is below the
@@ -954,7 +958,20 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
         // filter every leaf of the unit first; lane t keeps leaf t's results
         float r_thr = 0.0f, r_u = 0.0f;
         int r_m = 0, r_j = -1;
-        for (uint64_t q = unit; q; q &= q - 1) {
+        if (sn == 1 && !per_leaf) {
+            // a region (the group's cell) whose list holds one centroid: it is
+            // every point's nearest, and the region is assigned to it as a unit
+            float cc[3];
+            const float4 c4 = sh.sc[0];
+            f4_to(c4, cc);
+            if (mine) {
+                r_m = 1;
+                r_j = __float_as_int(c4.w);
+                r_u = box_maxd<D>(r.lo, r.hi, cc); // the leaf filter's U
+            }
+            st[ST_REGION_PTS] += wave_sum_i32(mine ? r.size : 0);
+        }
+        for (uint64_t q = (sn == 1 && !per_leaf) ? 0ull : unit; q; q &= q - 1) {
             const int t = __ffsll((unsigned long long)q) - 1;
             float blo[3], bhi[3];
 #pragma unroll

@@ -46,6 +46,7 @@ enum StatSlot {
     ST_DEFERRED = 8,      // leaves handed to the per-leaf pass
     ST_GROUP_OVF = 9,     // groups whose candidate list did not fit (searched leaf by leaf)
     ST_GROUP_SKIP = 10,   // groups with every leaf kept: no centroid-tree descent
+    ST_REGION_PTS = 11,   // points of groups (regions) whose candidate list held one centroid
 };
 
 // Device-side loop control of a context (ctl[]): the step kernels of a

@@ -30,7 +30,7 @@ STATS = np.dtype([("n_changed", "<i8"), ("dist_evals", "<i8"), ("brute_evals", "
                   ("single_cand_points", "<i8"), ("rechecked", "<i8"), ("cand_total", "<i8"),
                   ("leaves", "<i8"), ("sse", "<f8"), ("inter_leaf_points", "<i8"), ("inter_points", "<i8"),
                   ("fallback_points", "<i8"), ("deferred_leaves", "<i8"), ("group_overflows", "<i8"),
-                  ("groups_skipped", "<i8")])
+                  ("groups_skipped", "<i8"), ("region_points", "<i8")])
 
 
 @pytest.fixture(scope="module")
@@ -131,14 +131,16 @@ def test_emulated_fallback_paths(driver, tmp_path):
 
 def test_emulated_long_trajectory_inter_bounds(driver, tmp_path):
     """Ten steps: the exact sums are carried from step to step and moved
-    point by point or leaf by leaf, and the inter bounds keep leaves and
-    points; every step still equals the oracle."""
+    point by point or leaf by leaf, the inter bounds keep leaves and points,
+    and regions with a single candidate are assigned whole; every step still
+    equals the oracle."""
     x = gaussian_mixture_2d(5000, seed=83).astype(np.float32)
     c0 = init_centroids(x, 25, 84)
     got = _check(driver, tmp_path, x, c0, 10, KM_INDEXED)
     kept_leaf = sum(int(st["inter_leaf_points"]) for _, _, st in got[1:])
     kept_pt = sum(int(st["inter_points"]) for _, _, st in got[1:])
-    assert kept_leaf > 0 and kept_pt > 0, (kept_leaf, kept_pt)
+    region = sum(int(st["region_points"]) for _, _, st in got)
+    assert kept_leaf > 0 and kept_pt > 0 and region > 0, (kept_leaf, kept_pt, region)
     assert got[0][2]["inter_leaf_points"] == 0  # nothing is kept before the first assignment
 
 

@@ -85,6 +85,7 @@ def test_geo2d_1e6_every_point_every_iteration(ekm):
     # the pruning machinery is really in use at this size
     assert sum(s["inter_leaf_points"] for s in stats[1:]) > 0
     assert sum(s["single_cand_points"] for s in stats) > 0
+    assert sum(s["region_points"] for s in stats) > 0  # regions assigned whole
     _say("[fullsize] geo2d 1e6: kmeans_run until stable")
     dev = torch.device("cuda:0")
     ctx = ekm.kmeans_init(torch.from_numpy(x).to(dev), c0.shape[0])
