@@ -163,10 +163,21 @@ def kmeans_context_info(ctx: "Context") -> dict:
 
 
 class Context:
-    """Owns a km_ctx; released by ``kmeans_destroy`` (or when collected)."""
+    """Owns a km_ctx; released by ``kmeans_destroy`` (or when collected).
+
+    The library launches a context's work on the stream that was current at
+    ``kmeans_init``; the step calls check that it is still torch's current
+    stream, so that their inputs and outputs stay ordered with the caller's
+    work."""
 
     def __init__(self, handle: int, n: int, k: int, d: int):
         self.handle, self.n, self.k, self.d = handle, n, k, d
+        self.stream = _stream()
+
+    def check_stream(self):
+        if _stream() != self.stream:
+            raise ValueError("the current stream differs from the one this context was created on; "
+                             "switch back to it (torch.cuda.stream) before stepping the context")
 
     def close(self):
         if self.handle:
@@ -305,6 +316,7 @@ class Predictor:
 def kmeans_step(ctx: Context, c_in: torch.Tensor, c_out: torch.Tensor | None = None,
                 assign_out: torch.Tensor | None = None, stats: bool = False):
     """One Lloyd iteration; returns ``c_out`` (and a stats dict when ``stats``)."""
+    ctx.check_stream()
     if c_out is None:
         c_out = torch.empty_like(c_in)
     st = KmIterStats()
@@ -318,6 +330,7 @@ def kmeans_step(ctx: Context, c_in: torch.Tensor, c_out: torch.Tensor | None = N
 def kmeans_run(ctx: Context, c_inout: torch.Tensor, max_iter: int, stop_when_stable: bool = False,
                assign_out: torch.Tensor | None = None, per_iter: bool = False):
     """Up to ``max_iter`` iterations in place on ``c_inout``; returns (iterations, [stats])."""
+    ctx.check_stream()
     arr = (KmIterStats * max(1, max_iter))() if per_iter else None
     it = ctypes.c_int32(0)
     _check(load_library().kmeans_run(

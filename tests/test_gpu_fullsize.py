@@ -219,3 +219,21 @@ def test_too_wide_for_exact_sums_rejected(ekm):
     with pytest.raises(ekm.EKMError) as e:
         ekm.kmeans_init(torch.from_numpy(x).to(dev), 8)
     assert e.value.status == ekm.KM_ERR_NOT_EXACT
+
+
+def test_stream_mismatch_rejected(ekm):
+    """A context's work goes to the stream it was created on; stepping it
+    while another stream is current is refused by the binding."""
+    import torch
+    x = torch.rand(5000, 2, device="cuda")
+    ctx = ekm.kmeans_init(x, 10)
+    c = x[:10].double().clone()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with pytest.raises(ValueError):
+            ekm.kmeans_step(ctx, c)
+        with pytest.raises(ValueError):
+            ekm.kmeans_run(ctx, c, 2)
+    ekm.kmeans_step(ctx, c)  # back on the creation stream
+    torch.cuda.synchronize()
+    ctx.close()
