@@ -288,6 +288,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline timing only (for profiler runs)")
+    ap.add_argument("--only", choices=("surfaces", "distortion", "batched"),
+                    help="run one further leg alone and print its JSON (for profiler runs)")
+    ap.add_argument("--leg-iters", type=int, default=None,
+                    help="iterations of the surfaces leg with --only (default: its full count)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run the plain device copy (calibrates HBM byte counters) in --quick mode")
     args = ap.parse_args()
@@ -303,6 +307,12 @@ def main() -> int:
 
     ekm.load_library()
     dev = torch.device("cuda:0")
+    if args.only:
+        leg = {"surfaces": lambda: leg_surfaces(ekm, torch, dev, quick_iters=args.leg_iters),
+               "distortion": lambda: leg_distortion(ekm, torch, dev),
+               "batched": lambda: leg_batched(ekm, torch, dev)}[args.only]()
+        print(json.dumps(leg))
+        return 0
     x, c0, cfg = make_config(1)
     n, d = x.shape
     k = c0.shape[0]
