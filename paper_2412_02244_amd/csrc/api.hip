@@ -9,6 +9,7 @@
 #include <mutex>
 
 #include "ekm_internal.hpp"
+#include "finalize.hpp"
 
 namespace ekm {
 
@@ -98,7 +99,7 @@ static km_status check_config(const km_config *cfg, int64_t n, int64_t k)
 struct WsCounts {
     int64_t n = 0, k = 0, B = 1;
     int64_t L = 0, groups = 0;  // leaves, leaf groups
-    int64_t nodes = 0, cb_chunks = 0; // centroid-tree nodes and inter-bound chunks over all clouds
+    int64_t nodes = 0, pair_blocks = 0; // centroid-tree nodes and inter-bound pair-scan workgroups
 };
 
 // The workspace in the order the build allocates it: `build` (cloud tables,
@@ -128,8 +129,10 @@ static WsParts ws_parts(const km_config *cfg, const WsCounts &c)
         p.rest += al(2 * L, 16) + al(L * d * 2, 8) + al(L, 4);
     p.rest += al(n, 4) + al(k, 16) + al(k, 4) + al(1, 4) + al(k * d * 2, 8) + al(k, 4);
     p.rest += al(sse_blocks(n), 8) + al(NSTAT, 8) + al(1, 8) + al(k * d, 8);
+    p.rest += al(FIN_MAX_STAT_WG * (NSTAT + 1), 8) + al(1, 4); // statistics hand-over (finalize.hpp)
     if (indexed) // centroid trees, inter bounds, per-leaf state
-        p.rest += al(k, 16) + 2 * al(c.nodes, 16) + al(c.B, sizeof(TreeArgs)) + 2 * al(c.cb_chunks, 4) +
+        p.rest += al(k, 16) + 2 * al(c.nodes, 16) + al(c.B, sizeof(TreeArgs)) +
+                  al(c.pair_blocks * PAIR_WAVES, sizeof(PairItem)) +
                   3 * al(L, 4) + al(1, 4) + 3 * al(k, 4) + al(1, 4) + al(k * d, 8);
     p.rest += al(CTL_N, 4);
     const int64_t nblk = indexed ? (c.groups + 3) / 4 + HEAVY_BLOCKS : (n + 255) / 256;
@@ -152,6 +155,7 @@ static WsCounts ws_estimate(const km_config *cfg, int B, const int64_t *pt_off, 
     c.B = B;
     const bool packed =
         cfg->algo == KM_INDEXED && cfg->point_dtype == KM_F32 && !(cfg->flags & KM_FLAG_CELL_LEAVES);
+    bool small = true; // every cloud's tree is built in LDS, with the pair scan of the inter bound
     for (int b = 0; b < B; ++b) {
         const int64_t nb = pt_off[b + 1] - pt_off[b], kb = c_off[b + 1] - c_off[b];
         if (packed) {
@@ -166,8 +170,10 @@ static WsCounts ws_estimate(const km_config *cfg, int B, const int64_t *pt_off, 
         TreeArgs T;
         tree_layout(kb, T);
         c.nodes += T.nnodes;
-        c.cb_chunks += (kb + WAVE - 1) / WAVE;
+        small = small && kb <= TREE_SMALL_K;
     }
+    if (cfg->algo == KM_INDEXED && small)
+        c.pair_blocks = pair_plan(c_off, B, nullptr);
     return c;
 }
 
@@ -543,7 +549,9 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     ctx->acc = ctx_alloc<int64_t>(ctx, (size_t)k * ctx->d * 2);
     ctx->cnt = ctx_alloc<int32_t>(ctx, k);
     ctx->nblk_stat = assign_blocks(ctx);
-    ctx->stat_part = ctx_alloc<int64_t>(ctx, (size_t)ctx->nblk_stat * NSTAT);
+    ctx->stat_part = ctx_alloc_groups<int64_t>(ctx, (size_t)ctx->nblk_stat * NSTAT);
+    ctx->fin_part = ctx_alloc<int64_t>(ctx, (size_t)FIN_MAX_STAT_WG * (NSTAT + 1));
+    ctx->fin_ticket = ctx_alloc<int32_t>(ctx, 1);
     ctx->nblk_sse = sse_blocks(n);
     ctx->sse_part = ctx_alloc<double>(ctx, ctx->nblk_sse);
     ctx->stat_out = ctx_alloc<int64_t>(ctx, NSTAT);
@@ -554,33 +562,32 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     else
         ctx->stat_hist = nullptr;
     if (!ctx->a || !ctx->c32 || !ctx->cval || !ctx->cerr || !ctx->acc || !ctx->cnt || !ctx->stat_part ||
+        !ctx->fin_part || !ctx->fin_ticket ||
         !ctx->sse_part || !ctx->stat_out || !ctx->sse_out || !ctx->c_run || !ctx->stat_hist) {
         kmeans_destroy(ctx);
         return alloc_fail(nullptr);
     }
     if (cfg->algo == KM_INDEXED) {
         // one tree per cloud, in concatenated arrays (tree positions local,
-        // ids global), and the chunks of the inter-bound pair scan
+        // ids global), and the wave items of the inter-bound pair scan
         ctx->h_trees.assign(B, TreeArgs{});
         int64_t nn = 0;
-        std::vector<int32_t> chunk_cloud, chunk_first;
         for (int b = 0; b < B; ++b) {
             TreeArgs &T = ctx->h_trees[b];
             T.k = c_off[b + 1] - c_off[b];
             T.c0 = c_off[b];
             tree_layout(T.k, T);
             nn += T.nnodes;
-            for (int64_t j = 0; j < T.k; j += WAVE) {
-                chunk_cloud.push_back(b);
-                chunk_first.push_back((int32_t)(T.c0 + j));
-            }
+        }
+        std::vector<PairItem> pairs;
+        if (small_trees(ctx)) {
+            ctx->npair_blocks = pair_plan(c_off, B, &pairs);
+            ctx->tree_kcap = small_tree_cap(c_off, B);
         }
         float4 *cs = ctx_alloc<float4>(ctx, k), *nlo = ctx_alloc<float4>(ctx, nn), *nhi = ctx_alloc<float4>(ctx, nn);
         ctx->trees = ctx_alloc<TreeArgs>(ctx, B);
-        ctx->ncb_chunks = (int64_t)chunk_cloud.size();
-        ctx->cb_chunk_cloud = ctx_alloc<int32_t>(ctx, ctx->ncb_chunks);
-        ctx->cb_chunk_first = ctx_alloc<int32_t>(ctx, ctx->ncb_chunks);
-        if (!cs || !nlo || !nhi || !ctx->trees || !ctx->cb_chunk_cloud || !ctx->cb_chunk_first) {
+        ctx->pair_items = ctx_alloc<PairItem>(ctx, pairs.size());
+        if (!cs || !nlo || !nhi || !ctx->trees || (!pairs.empty() && !ctx->pair_items)) {
             kmeans_destroy(ctx);
             return alloc_fail(nullptr);
         }
@@ -594,12 +601,9 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
         ctx->tree = ctx->h_trees[0];
         if (!hip_ok(hipMemcpyAsync(ctx->trees, ctx->h_trees.data(), B * sizeof(TreeArgs), hipMemcpyHostToDevice, st),
                     "hipMemcpyAsync") ||
-            !hip_ok(hipMemcpyAsync(ctx->cb_chunk_cloud, chunk_cloud.data(), chunk_cloud.size() * sizeof(int32_t),
-                                   hipMemcpyHostToDevice, st),
-                    "hipMemcpyAsync") ||
-            !hip_ok(hipMemcpyAsync(ctx->cb_chunk_first, chunk_first.data(), chunk_first.size() * sizeof(int32_t),
-                                   hipMemcpyHostToDevice, st),
-                    "hipMemcpyAsync") ||
+            (!pairs.empty() && !hip_ok(hipMemcpyAsync(ctx->pair_items, pairs.data(), pairs.size() * sizeof(PairItem),
+                                                      hipMemcpyHostToDevice, st),
+                                       "hipMemcpyAsync")) ||
             !hip_ok(hipStreamSynchronize(st), "hipStreamSynchronize")) { // the host vectors go out of scope
             kmeans_destroy(ctx);
             return KM_ERR_HIP;
@@ -654,6 +658,7 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
               hip_ok(hipMemsetAsync(ctx->cerr, 0, sizeof(float), st), "hipMemsetAsync") &&
               hip_ok(hipMemsetAsync(ctx->acc, 0, (size_t)k * ctx->d * 2 * sizeof(int64_t), st), "hipMemsetAsync") &&
               hip_ok(hipMemsetAsync(ctx->cnt, 0, k * sizeof(int32_t), st), "hipMemsetAsync") &&
+              hip_ok(hipMemsetAsync(ctx->fin_ticket, 0, sizeof(int32_t), st), "hipMemsetAsync") &&
               hip_ok(hipStreamSynchronize(st), "kmeans_init: hipStreamSynchronize");
     if (!ok) {
         kmeans_destroy(ctx);

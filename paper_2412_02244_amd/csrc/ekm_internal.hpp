@@ -527,6 +527,13 @@ __device__ inline int cloud_of(const int64_t *off, int B, int64_t i)
     return lo;
 }
 
+// One wave's share of the inter-bound pair scan (see pair_plan in tree.hip).
+struct alignas(16) PairItem {
+    int32_t first;  // global id of the chunk's first centroid (one per lane), -1: an idle wave
+    int32_t c0, c1; // the chunk's cloud: centroids [c0, c1)
+    int32_t sl;     // slice t | (slices s << 8): the wave scans c0 + t, c0 + t + s, ...
+};
+
 // Implicit 8-ary centroid tree of one cloud (see tree.hip).
 struct TreeArgs {
     float4 *cs;               // [k] fl32 centroids in tree order, w = global centroid id bits
@@ -571,8 +578,11 @@ struct km_ctx {
     std::vector<ekm::Grid> h_grids;
     int32_t *leaf_cloud = nullptr;   // [L]
     int32_t *group_cloud = nullptr;  // [ngroups]
-    int64_t ncb_chunks = 0;          // inter-bound pair scan: runs of up to 64 centroids of one cloud
-    int32_t *cb_chunk_cloud = nullptr, *cb_chunk_first = nullptr;
+    // inter-bound pair scan (clouds of at most TREE_SMALL_K centroids): workgroups of the tree
+    // launch after its B tree workgroups, PAIR_WAVES wave items each (see pair_plan)
+    int64_t npair_blocks = 0;
+    ekm::PairItem *pair_items = nullptr;
+    int tree_kcap = 64;              // LDS capacity of the small-k tree launch (small_tree_cap)
     int tile = 1024;     // brute-path LDS tile (centroids)
     int S = 0;           // fixed-point scale exponent
     int fix64 = 0;       // every point's fixed-point coordinate fits FIX64_BITS bits
@@ -614,6 +624,8 @@ struct km_ctx {
     int64_t *stat_part = nullptr; // [nblk][NSTAT]
     int64_t nblk_sse = 0;
     double *sse_part = nullptr;   // [nblk_sse] objective partials of the SSE pass
+    int64_t *fin_part = nullptr;  // [FIN_MAX_STAT_WG][NSTAT + 1] totals of the statistics-folding workgroups
+    int32_t *fin_ticket = nullptr; // [1] folding workgroups done (0 between steps)
     int64_t *stat_out = nullptr;  // [NSTAT]
     double *sse_out = nullptr;    // [1]
     int64_t *host_stat = nullptr; // pinned [NSTAT + 1]
@@ -623,6 +635,7 @@ struct km_ctx {
     uint32_t *scan_tmp = nullptr;
     ekm::Scratch mem;
     char *arena = nullptr; // current arena (see ctx_alloc)
+    bool groups_in_arena = false; // the current arena holds the model's group part (ctx_alloc_groups)
     size_t arena_size = 0, arena_used = 0;
     int steps_done = 0;
     int32_t *ctl = nullptr;       // [CTL_N] device-side loop control
@@ -677,6 +690,22 @@ T *ctx_alloc(km_ctx *ctx, size_t count)
     return (T *)p;
 }
 
+// A buffer of the workspace model's group part (leaf groups, statistics
+// rows): from the arena when the arena was sized with that part, else an
+// allocation of its own, so that it never takes the arena space of a later
+// buffer of the other parts.
+template <class T>
+T *ctx_alloc_groups(km_ctx *ctx, size_t count)
+{
+    if (ctx->groups_in_arena)
+        return ctx_alloc<T>(ctx, count);
+    char *a = ctx->arena;
+    ctx->arena = nullptr;
+    T *p = ctx_alloc<T>(ctx, count);
+    ctx->arena = a;
+    return p;
+}
+
 // Starts a new arena of `bytes` (the rest of the previous one is unused).
 inline bool ctx_arena(km_ctx *ctx, size_t bytes)
 {
@@ -710,6 +739,9 @@ km_status build_leaves(km_ctx *ctx, const void *points);
 km_status build_centroid_tree(km_ctx *ctx, const double *c_in);
 bool small_trees(const km_ctx *ctx);
 constexpr int TREE_SMALL_K = 4096; // largest cloud whose tree one workgroup builds in LDS
+constexpr int PAIR_WAVES = 16;     // waves per pair-scan workgroup (the tree workgroup's size)
+int64_t pair_plan(const int64_t *c_off, int B, std::vector<PairItem> *items);
+int small_tree_cap(const int64_t *c_off, int B);
 hipError_t tree_setup();
 void tree_layout(int64_t k, TreeArgs &T);
 

@@ -11,6 +11,7 @@ constexpr int FIN_THREADS = 256;
 struct FinShared {
     long long red[NSTAT][FIN_THREADS];
     double dred[FIN_THREADS];
+    int last;
 };
 
 // Cluster j: c_out[j] = RN(exact sum) / count (IEEE FP64 division), or
@@ -37,11 +38,26 @@ __device__ inline void fin_cluster(int64_t j, const double *c_in, double *c_out,
         cnt[j] = 0;
 }
 
+// Workgroups that fold the statistics rows: one per `rows` rows (8 per
+// thread, or a few rows with KM_FLAG_SMALL_LISTS, which tests the
+// hand-over), at most FIN_MAX_STAT_WG.  Below that a single workgroup
+// folds them all: the hand-over costs more than it saves.
+constexpr int FIN_MAX_STAT_WG = 256;
+inline int fin_rows_per_wg(uint32_t flags) { return (flags & KM_FLAG_SMALL_LISTS) ? 8 : 8 * FIN_THREADS; }
+inline int64_t fin_stat_wgs(int64_t nblk, int rows)
+{
+    const int64_t p = (nblk + rows - 1) / rows;
+    return p < 1 ? 1 : (p > FIN_MAX_STAT_WG ? FIN_MAX_STAT_WG : p);
+}
+
 struct FinStats {
     int64_t nblk;               // rows of per-block counters
     const int64_t *stat_part;   // [nblk][NSTAT]
     int64_t nsse;               // objective partials (0: none)
     const double *sse_part;
+    int64_t nwg;                // folding workgroups (fin_stat_wgs)
+    int64_t *wg_part;           // [nwg][NSTAT + 1]: each one's totals (the objective's bits last)
+    int32_t *ticket;            // folding workgroups done this step (0 between steps)
     int64_t *stat_out;          // [NSTAT]
     double *sse_out;
     unsigned *cmax_bits;        // reset for the next step's centroid tree
@@ -52,17 +68,26 @@ struct FinStats {
     int64_t hist_cap;
 };
 
-// The step's statistics (a workgroup of FIN_THREADS threads): each thread
-// folds whole rows of the per-block partials, then a fixed-shape tree
-// combines the threads, so the totals do not depend on timing.  Also the
+// The step's statistics, folded by F.nwg workgroups of FIN_THREADS threads
+// (w = 0 .. nwg - 1).  Workgroup w folds rows [w R, (w + 1) R) of the
+// per-block partials (and the same share of the objective partials), each
+// thread whole rows, then a fixed-shape tree combines its threads.  With
+// several workgroups, each writes its totals, and the last one to finish
+// (a ticket counter) adds them up in workgroup order.  Integer counters
+// are exact in any order and the objective is summed in a fixed order, so
+// the totals do not depend on timing.  The last workgroup also runs the
 // loop control: the run ends after max_iter steps, or at the first step
 // t >= 2 whose assignment equals that of step t - 1.
-__device__ inline void fin_stats(FinShared &fs, const FinStats &F)
+__device__ inline void fin_stats(FinShared &fs, const FinStats &F, int64_t w)
 {
+    const int64_t R = (F.nblk + F.nwg - 1) / F.nwg, Rs = (F.nsse + F.nwg - 1) / F.nwg;
+    const int64_t r1 = (w + 1) * R < F.nblk ? (w + 1) * R : F.nblk;
+    const int64_t s1 = (w + 1) * Rs < F.nsse ? (w + 1) * Rs : F.nsse;
     long long acc8[NSTAT];
     for (int q = 0; q < NSTAT; ++q)
         acc8[q] = 0;
-    for (int64_t b = threadIdx.x; b < F.nblk; b += FIN_THREADS) {
+#pragma unroll 4 // independent rows: several in flight at once
+    for (int64_t b = w * R + threadIdx.x; b < r1; b += FIN_THREADS) {
         const longlong2 *row = (const longlong2 *)(F.stat_part + b * NSTAT);
 #pragma unroll
         for (int q = 0; q < NSTAT / 2; ++q) {
@@ -72,7 +97,7 @@ __device__ inline void fin_stats(FinShared &fs, const FinStats &F)
         }
     }
     double s = 0.0;
-    for (int64_t b = threadIdx.x; b < F.nsse; b += FIN_THREADS)
+    for (int64_t b = w * Rs + threadIdx.x; b < s1; b += FIN_THREADS)
         s += F.sse_part[b];
     for (int q = 0; q < NSTAT; ++q)
         fs.red[q][threadIdx.x] = acc8[q];
@@ -83,6 +108,38 @@ __device__ inline void fin_stats(FinShared &fs, const FinStats &F)
             for (int q = 0; q < NSTAT; ++q)
                 fs.red[q][threadIdx.x] += fs.red[q][threadIdx.x + o];
             fs.dred[threadIdx.x] += fs.dred[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (F.nwg > 1) {
+        // hand this workgroup's totals over; the last workgroup folds them
+        if (threadIdx.x < NSTAT)
+            F.wg_part[w * (NSTAT + 1) + threadIdx.x] = fs.red[threadIdx.x][0];
+        if (threadIdx.x == NSTAT)
+            F.wg_part[w * (NSTAT + 1) + NSTAT] = __double_as_longlong(fs.dred[0]);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            fs.last = atomicAdd(F.ticket, 1) == (int)F.nwg - 1;
+        __syncthreads();
+        if (!fs.last)
+            return;
+        __threadfence();
+        if (threadIdx.x <= NSTAT) {
+            const int q = threadIdx.x;
+            long long t = 0;
+            double d = 0.0;
+            for (int64_t u = 0; u < F.nwg; ++u) {
+                const long long v = __atomic_load_n(F.wg_part + u * (NSTAT + 1) + q, __ATOMIC_RELAXED);
+                if (q < NSTAT)
+                    t += v;
+                else
+                    d += __longlong_as_double(v);
+            }
+            if (q < NSTAT)
+                fs.red[q][0] = t;
+            else
+                fs.dred[0] = d;
         }
         __syncthreads();
     }
@@ -105,6 +162,8 @@ __device__ inline void fin_stats(FinShared &fs, const FinStats &F)
             *F.drift_max = 0u; // and the largest drift
         if (F.heavy_cnt)
             *F.heavy_cnt = 0; // the deferred-leaf list of the next step starts empty
+        if (F.nwg > 1)
+            *F.ticket = 0;
     }
 }
 

@@ -582,6 +582,7 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
     ctx->L = L;
     // the rest of the workspace in one allocation, now that its sizes are
     // known (the leaf groups too with default leaves)
+    ctx->groups_in_arena = packed;
     if (!ctx_arena(ctx, ctx_bytes_after_counts(ctx, L, ncells, packed))) {
         set_error("kmeans_init: device allocation failed");
         return KM_ERR_OOM;
@@ -607,9 +608,9 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
     }
     if (packed) { // one group per group cell
         ctx->ngroups = ncells;
-        ctx->group_leaf = ctx_alloc<int32_t>(ctx, ncells + 1);
-        ctx->group_box = ctx_alloc<float4>(ctx, 2 * ncells);
-        ctx->group_cloud = ctx_alloc<int32_t>(ctx, ncells);
+        ctx->group_leaf = ctx_alloc_groups<int32_t>(ctx, ncells + 1);
+        ctx->group_box = ctx_alloc_groups<float4>(ctx, 2 * ncells);
+        ctx->group_cloud = ctx_alloc_groups<int32_t>(ctx, ncells);
         if (!ctx->group_leaf || !ctx->group_box || !ctx->group_cloud) {
             set_error("kmeans_init: device allocation failed");
             return KM_ERR_OOM;
@@ -655,9 +656,9 @@ static km_status build_leaves_t(km_ctx *ctx, const T *x)
         }
         if (ok) {
             ctx->ngroups = (int64_t)last[0] + last[1];
-            ctx->group_leaf = ctx_alloc<int32_t>(ctx, ctx->ngroups + 1);
-            ctx->group_box = ctx_alloc<float4>(ctx, 2 * ctx->ngroups);
-            ctx->group_cloud = ctx_alloc<int32_t>(ctx, ctx->ngroups);
+            ctx->group_leaf = ctx_alloc_groups<int32_t>(ctx, ctx->ngroups + 1);
+            ctx->group_box = ctx_alloc_groups<float4>(ctx, 2 * ctx->ngroups);
+            ctx->group_cloud = ctx_alloc_groups<int32_t>(ctx, ctx->ngroups);
             if (!ctx->group_leaf || !ctx->group_box || !ctx->group_cloud) {
                 if (tmp)
                     (void)hipFree(tmp);

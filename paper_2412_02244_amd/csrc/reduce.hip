@@ -8,9 +8,10 @@
 // keeps its previous centroid.  On the indexed path the sums persist from
 // step to step (moves between clusters update them) and are only brought
 // back to their normal limb form here; on the brute path every step sums
-// afresh and they are cleared here.  The last block folds the per-block
-// statistics and objective partials in a fixed order, so the reported
-// counters and objective are deterministic.
+// afresh and they are cleared here.  The workgroups after the cluster ones
+// fold the per-block statistics and objective partials (fin_stats): exact
+// integer counters, and the objective summed in a fixed order, so the
+// reported counters and objective are deterministic.
 #include "finalize.hpp"
 
 namespace ekm {
@@ -23,8 +24,9 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, do
     // The cluster blocks run even when the run is over: every kernel of such
     // a step returned at once, so the sums are those of the last real step
     // and the centroids written are the same values again (the brute path's
-    // cleared sums give c_out = c_in).  Only the statistics block, which
-    // alone sets CTL_STOP, tests it, so no block races that write.
+    // cleared sums give c_out = c_in).  Only the statistics workgroups test
+    // it, each before it takes its ticket, and only the last of them sets
+    // it, so no workgroup races that write.
     if ((int64_t)blockIdx.x < nclusterblocks) {
         int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (j < k)
@@ -32,9 +34,9 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(const double *c_in, do
         return;
     }
     if (F.ctl[CTL_STOP])
-        return; // a step after the end of the run: nothing to record
+        return; // a step after the end of the run: nothing to record (no workgroup takes a ticket)
     __shared__ FinShared fs;
-    fin_stats(fs, F);
+    fin_stats(fs, F, (int64_t)blockIdx.x - nclusterblocks);
 }
 
 // Caller order and cloud-local centroid ids (position i of the Morton order
@@ -65,6 +67,9 @@ FinStats fin_stats_args(km_ctx *ctx, bool with_sse)
     F.ctl = ctx->ctl;
     F.stat_hist = ctx->stat_hist;
     F.hist_cap = ctx->hist_cap;
+    F.nwg = fin_stat_wgs(F.nblk, fin_rows_per_wg(ctx->cfg.flags));
+    F.wg_part = ctx->fin_part;
+    F.ticket = ctx->fin_ticket;
     return F;
 }
 
@@ -75,11 +80,11 @@ km_status run_finalize(km_ctx *ctx, const double *c_in, double *c_out, int32_t *
     const int reset = ctx->cfg.algo == KM_INDEXED ? 0 : 1;
     const FinStats F = fin_stats_args(ctx, with_sse);
     if (ctx->d == 2)
-        hipLaunchKernelGGL(k_finalize<2>, dim3((unsigned)(ncb + 1)), dim3(FIN_THREADS), 0, st, c_in, c_out, ctx->k,
-                           ctx->acc, ctx->cnt, ctx->S, reset, ncb, F);
+        hipLaunchKernelGGL(k_finalize<2>, dim3((unsigned)(ncb + F.nwg)), dim3(FIN_THREADS), 0, st, c_in, c_out,
+                           ctx->k, ctx->acc, ctx->cnt, ctx->S, reset, ncb, F);
     else
-        hipLaunchKernelGGL(k_finalize<3>, dim3((unsigned)(ncb + 1)), dim3(FIN_THREADS), 0, st, c_in, c_out, ctx->k,
-                           ctx->acc, ctx->cnt, ctx->S, reset, ncb, F);
+        hipLaunchKernelGGL(k_finalize<3>, dim3((unsigned)(ncb + F.nwg)), dim3(FIN_THREADS), 0, st, c_in, c_out,
+                           ctx->k, ctx->acc, ctx->cnt, ctx->S, reset, ncb, F);
     if (!hip_ok(hipGetLastError(), "finalize launch"))
         return KM_ERR_HIP;
     return assign_out ? scatter_assignment(ctx, assign_out) : KM_OK;

@@ -165,6 +165,100 @@ __device__ inline float nn_bound(bool have_prev, float cb_hi_prev, float drift_j
 __device__ inline float err_of(float cmax) { return cmax * 0x1p-24f * (1.0f + 0x1p-20f) + 0x1p-100f; }
 
 // ------------------------------------------------------------------ small k
+// Inter bound of Eq. (3) for clouds of k <= SMALL_K: for every centroid, the
+// smallest FP32 squared distance from fl32(c_j) to another fl32 centroid of
+// its cloud, by scanning all pairs.  A workgroup of PAIR_WAVES waves, wave w
+// taking items[w]: lane l holds centroid first + l of a chunk and scans one
+// slice of the chunk's cloud.  The s slices of a chunk sit in consecutive
+// waves of one workgroup, so their minima meet in LDS and the slice-0 wave
+// writes the result (no atomics, nothing to clear beforehand).  The fl32
+// copies are rounded here from the FP64 centroids, as the tree rounds them.
+// The keep tests turn cb_s into a lower bound on the exact distance between
+// the FP64 centroids.
+//   pmin: LDS, PAIR_WAVES * WAVE floats.
+template <int D>
+__device__ void pair_block(const double *c_all, const PairItem *items, unsigned *cb_s, float *pmin)
+{
+    const int lane = lane_id(), wid = (int)threadIdx.x / WAVE;
+    const PairItem it = items[wid];
+    const int first = uniform_int(it.first), c0 = uniform_int(it.c0), c1 = uniform_int(it.c1);
+    const int sl = uniform_int(it.sl);
+    const int t = sl & 0xff, s = sl >> 8;
+    const int j = first + lane;
+    float b0 = INFINITY, b1 = INFINITY; // two chains: shorter dependences
+    if (first >= 0) {
+        float cj[3] = {0.0f, 0.0f, 0.0f};
+        if (j < c1)
+            for (int a = 0; a < D; ++a)
+                cj[a] = (float)c_all[(int64_t)j * D + a];
+        // the slice's centroids i = c0 + t + m s, 64 at a time: lane l loads
+        // number m0 + l, then each is broadcast to the wave (readlane)
+        const int M = (c1 - c0 - t + s - 1) / s;
+        for (int m0 = 0; m0 < M; m0 += WAVE) {
+            const int i_l = c0 + t + (m0 + lane) * s;
+            float q[3] = {0.0f, 0.0f, 0.0f};
+            if (m0 + lane < M)
+                for (int a = 0; a < D; ++a)
+                    q[a] = (float)c_all[(int64_t)i_l * D + a];
+            const int cnt = M - m0 < WAVE ? M - m0 : WAVE;
+            auto dist = [&](int u) {
+                float p[3] = {0.0f, 0.0f, 0.0f};
+                for (int a = 0; a < D; ++a)
+                    p[a] = rl_f(q[a], u);
+                const float sv = sqdist32<D>(cj, p);
+                return c0 + t + (m0 + u) * s != j ? sv : INFINITY;
+            };
+            int u = 0;
+            for (; u + 1 < cnt; u += 2) {
+                b0 = fminf(b0, dist(u));
+                b1 = fminf(b1, dist(u + 1));
+            }
+            if (u < cnt)
+                b0 = fminf(b0, dist(u));
+        }
+    }
+    pmin[wid * WAVE + lane] = fminf(b0, b1);
+    __syncthreads();
+    if (first >= 0 && t == 0 && j < c1) {
+        float m = pmin[wid * WAVE + lane];
+        for (int w = 1; w < s; ++w)
+            m = fminf(m, pmin[(wid + w) * WAVE + lane]);
+        cb_s[j] = __float_as_uint(m); // non-negative floats order like their bit patterns
+    }
+}
+
+// The wave items of the pair scan over clouds [0, B) (c_off: B + 1 host
+// offsets), PAIR_WAVES per workgroup; returns the workgroup count and, if
+// items is given, fills it.  A chunk is up to 64 consecutive centroids of one
+// cloud.  Its cloud is split into s slices, s the smallest power of two with
+// s * PAIR_SCAN >= k_b (at most PAIR_WAVES), so a wave scans about
+// PAIR_SCAN centroids; the s waves of a chunk start at a multiple of s and
+// therefore share a workgroup.  Unused waves are idle (first = -1).
+constexpr int PAIR_SCAN = 128;
+int64_t pair_plan(const int64_t *c_off, int B, std::vector<PairItem> *items)
+{
+    int64_t pos = 0; // waves placed
+    for (int b = 0; b < B; ++b) {
+        const int64_t c0 = c_off[b], c1 = c_off[b + 1], kb = c1 - c0;
+        int s = 1;
+        while (s < PAIR_WAVES && (int64_t)s * PAIR_SCAN < kb)
+            s *= 2;
+        for (int64_t j = c0; j < c1; j += WAVE) {
+            const int64_t at = (pos + s - 1) / s * s;
+            if (items) {
+                items->resize((size_t)at, PairItem{-1, 0, 0, 0});
+                for (int t = 0; t < s; ++t)
+                    items->push_back(PairItem{(int32_t)j, (int32_t)c0, (int32_t)c1, t | (s << 8)});
+            }
+            pos = at + s;
+        }
+    }
+    const int64_t nblk = (pos + PAIR_WAVES - 1) / PAIR_WAVES;
+    if (items)
+        items->resize((size_t)(nblk * PAIR_WAVES), PairItem{-1, 0, 0, 0});
+    return nblk;
+}
+
 // Everything in one workgroup, LDS-resident after one read of the centroids:
 // prep, the tree order, the tree-ordered copy and every node box; global
 // memory is only written (and, between re-sorts, the previous order read).
@@ -174,30 +268,39 @@ __device__ inline float err_of(float cmax) { return cmax * 0x1p-24f * (1.0f + 0x
 // centroids.  Any grouping of the centroids gives exact boxes, so the order
 // only affects how tight the boxes are (centroids move little from step to
 // step), never which centroids are candidates.
-// One workgroup per cloud (blockIdx.x): its centroids are [T.c0, T.c0 + T.k)
-// of the concatenated arrays, with tree positions local to the cloud and
-// global ids in cs[].w.
+// One workgroup per cloud (blockIdx.x < nclouds): its centroids are [T.c0,
+// T.c0 + T.k) of the concatenated arrays, with tree positions local to the
+// cloud and global ids in cs[].w.  The workgroups after those run the pair
+// scan of the inter bound (pair_block), which reads only the FP64 centroids,
+// so both run side by side in one launch.
+static_assert(TREE_WAVES == PAIR_WAVES, "a pair-scan workgroup is a tree workgroup");
 template <int D>
 __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all, const TreeArgs *trees,
                                                              const Grid *grids, float4 *c32, unsigned *cmax_bits,
                                                              unsigned *cb_s, double *c_prev_all, unsigned *drift_max,
+                                                             const PairItem *pairs, int nclouds, int kcap,
                                                              const int32_t *ctl)
 {
     if (ctl[CTL_STOP])
         return; // the run is over (the whole workgroup returns)
+    extern __shared__ unsigned char smem[];
+    if ((int)blockIdx.x >= nclouds) {
+        pair_block<D>(c_all, pairs + (int64_t)(blockIdx.x - nclouds) * PAIR_WAVES, cb_s, (float *)smem);
+        return;
+    }
     const int have_prev = uniform_int(ctl[CTL_STEPS] > 0 ? 1 : 0);
     const TreeArgs &T = trees[blockIdx.x];
     const Grid g = grids[blockIdx.x];
     const int64_t c0 = T.c0, k = T.k;
     const double *c = c_all + c0 * D;
     const int resort = uniform_int(ctl[CTL_STEPS] % TREE_RESORT == 0 ? 1 : 0);
-    extern __shared__ unsigned char smem[];
-    float4 *cq = (float4 *)smem;              // [SMALL_K] fl32 centroids, caller order
-    uint32_t *key = (uint32_t *)(cq + SMALL_K); // [SMALL_K]
-    uint32_t *id = key + SMALL_K;             // [SMALL_K]
-    uint32_t *key2 = id + SMALL_K;            // [SMALL_K]
-    uint32_t *id2 = key2 + SMALL_K;           // [SMALL_K]
-    uint32_t *wcnt = id2 + SMALL_K;           // [TREE_WAVES][256]
+    // kcap: the largest cloud of the launch, rounded up (small_tree_lds)
+    float4 *cq = (float4 *)smem;              // [kcap] fl32 centroids, caller order
+    uint32_t *key = (uint32_t *)(cq + kcap);  // [kcap]
+    uint32_t *id = key + kcap;                // [kcap]
+    uint32_t *key2 = id + kcap;               // [kcap]
+    uint32_t *id2 = key2 + kcap;              // [kcap]
+    uint32_t *wcnt = id2 + kcap;              // [TREE_WAVES][256]
     uint32_t *base = wcnt + TREE_WAVES * 256; // [256]
     __shared__ float red[TREE_WAVES], dred[TREE_WAVES];
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / WAVE;
@@ -218,7 +321,6 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
             c_prev[j * D + i] = c[j * D + i];
         cq[j] = q4;
         c32[c0 + j] = q4;
-        cb_s[c0 + j] = 0x7f800000u; // +inf: k_cb_pairs takes the minimum
         key[j] = kb >> shift;
         // the order to keep: tree position j held centroid T.cs[j].w (a global id)
         id[j] = resort ? (uint32_t)j : (uint32_t)(__float_as_int(T.cs[j].w) - (int)c0);
@@ -311,7 +413,7 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
     }
     __syncthreads();
     // sorted ids are back in `id`; node boxes go to LDS (over key2/id2,
-    // free now: at most 2 * SMALL_K / TREE_BUCKET float4 pairs) and out
+    // free now: room for kcap / 4 float4, see small_tree_lds) and out
     float4 *nlo = (float4 *)key2, *nhi = nlo + T.nnodes;
     for (int t = tid; t < kk; t += TREE_THREADS) {
         int cid = (int)id[t];
@@ -347,49 +449,6 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
         }
         __syncthreads();
     }
-}
-
-// Inter bound of Eq. (3) for k <= SMALL_K: for every centroid, the smallest
-// FP32 squared distance to another centroid (both fl32), by scanning all
-// pairs.  Workgroup (x, y): centroids 64x .. 64x + 63 (one per lane), each
-// of its four waves the others i = 4y + w, 4y + w + 4 CB_SLICES, ...; the
-// partial minima meet through an atomic minimum on the float bits
-// (non-negative floats order like their bit patterns).  cb_s must hold
-// +inf beforehand (the tree kernel writes it).  The keep tests turn cb_s
-// into a lower bound on the exact distance between the FP64 centroids.
-constexpr int CB_THREADS = 256;
-constexpr int CB_SLICES = 16;
-//   chunk x: the up-to-64 centroids starting at global id chunk_first[x] of
-//   cloud chunk_cloud[x]; only that cloud's centroids are scanned.
-template <int D>
-__global__ void __launch_bounds__(CB_THREADS) k_cb_pairs(const float4 *c32, const TreeArgs *trees,
-                                                         const int32_t *chunk_cloud, const int32_t *chunk_first,
-                                                         unsigned *cb_s, const int32_t *ctl)
-{
-    if (ctl[CTL_STOP])
-        return;
-    const int lane = lane_id();
-    const TreeArgs &T = trees[chunk_cloud[blockIdx.x]];
-    const int64_t c0 = T.c0, c1 = T.c0 + T.k;
-    const int64_t j = (int64_t)chunk_first[blockIdx.x] + lane;
-    const int64_t stride = (int64_t)CB_SLICES * (CB_THREADS / WAVE);
-    const int64_t k = c1;
-    float cj[3] = {0.0f, 0.0f, 0.0f};
-    if (j < k)
-        f4_to3(c32[j], cj);
-    float best[2] = {INFINITY, INFINITY};
-    int u = 0;
-    for (int64_t i = c0 + (int64_t)blockIdx.y * (CB_THREADS / WAVE) + threadIdx.x / WAVE; i < k;
-         i += stride, u ^= 1) {
-        float q[3];
-        f4_to3(c32[i], q); // the same address in every lane: one broadcast load
-        const float sv = sqdist32<D>(cj, q);
-        if (i != j)
-            best[u] = fminf(best[u], sv); // two chains: shorter dependences
-    }
-    const float m = fminf(best[0], best[1]);
-    if (j < k && m < INFINITY)
-        atomicMin(cb_s + j, __float_as_uint(m));
 }
 
 // ------------------------------------------------------------------ large k
@@ -506,13 +565,38 @@ __global__ void __launch_bounds__(256) k_tree_level(TreeArgs T, int l)
     T.node_hi[off + i] = hi;
 }
 
-static size_t small_tree_lds()
+// LDS of the small-k tree launch for clouds of at most kcap centroids (a
+// multiple of 64): fl32 copies, two key/id buffers, the per-wave digit
+// counts and the digit bases.  The pair-scan workgroups use its first
+// PAIR_WAVES * WAVE floats.
+static size_t small_tree_lds(int kcap)
 {
-    return (size_t)SMALL_K * 16 + (size_t)SMALL_K * 16 + (size_t)TREE_WAVES * 256 * 4 + 256 * 4;
+    return (size_t)kcap * 16 + (size_t)kcap * 16 + (size_t)TREE_WAVES * 256 * 4 + 256 * 4;
 }
-// The node boxes of a k <= SMALL_K tree fit in the key2/id2 region.
+static_assert(PAIR_WAVES * WAVE * 4 <= TREE_WAVES * 256 * 4, "the pair minima fit the smallest tree LDS");
+
+// kcap of a context: its largest cloud, rounded up to a multiple of 64, and
+// large enough that every cloud's node boxes (32 bytes a node) fit in the
+// key2/id2 region (8 kcap bytes).
+int small_tree_cap(const int64_t *c_off, int B)
+{
+    int64_t m = 0, nodes = 0;
+    for (int b = 0; b < B; ++b) {
+        const int64_t kb = c_off[b + 1] - c_off[b];
+        TreeArgs T;
+        tree_layout(kb, T);
+        m = kb > m ? kb : m;
+        nodes = T.nnodes > nodes ? T.nnodes : nodes;
+    }
+    int64_t kcap = (m + 63) / 64 * 64;
+    if (kcap < 64)
+        kcap = 64;
+    while (nodes * 32 > kcap * 8)
+        kcap += 64;
+    return (int)kcap;
+}
 static_assert(2 * (SMALL_K / TREE_BUCKET + SMALL_K / TREE_BUCKET / 7 + 8) * 16 <= SMALL_K * 8,
-              "node boxes of the small tree fit in LDS");
+              "node boxes of the largest small tree fit in LDS");
 
 // Every cloud's tree is built by one workgroup (k of each cloud at most SMALL_K).
 bool small_trees(const km_ctx *ctx)
@@ -530,23 +614,15 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
     unsigned *cmax = (unsigned *)ctx->cerr;
     const int32_t *hp = ctx->ctl;
     if (ctx->cfg.algo == KM_INDEXED && small_trees(ctx)) {
-        const dim3 gb((unsigned)ctx->ncb_chunks, CB_SLICES);
-        const unsigned nb = (unsigned)ctx->B;
-        if (ctx->d == 2) {
-            hipLaunchKernelGGL(k_tree_small<2>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(), st, c_in,
+        const unsigned nb = (unsigned)(ctx->B + ctx->npair_blocks);
+        if (ctx->d == 2)
+            hipLaunchKernelGGL(k_tree_small<2>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(ctx->tree_kcap), st, c_in,
                                (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s,
-                               ctx->c_prev, ctx->drift_max, hp);
-            hipLaunchKernelGGL(k_cb_pairs<2>, gb, dim3(CB_THREADS), 0, st, (const float4 *)ctx->c32,
-                               (const TreeArgs *)ctx->trees, (const int32_t *)ctx->cb_chunk_cloud,
-                               (const int32_t *)ctx->cb_chunk_first, ctx->cb_s, hp);
-        } else {
-            hipLaunchKernelGGL(k_tree_small<3>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(), st, c_in,
+                               ctx->c_prev, ctx->drift_max, (const PairItem *)ctx->pair_items, ctx->B, ctx->tree_kcap, hp);
+        else
+            hipLaunchKernelGGL(k_tree_small<3>, dim3(nb), dim3(TREE_THREADS), small_tree_lds(ctx->tree_kcap), st, c_in,
                                (const TreeArgs *)ctx->trees, (const Grid *)ctx->grids, ctx->c32, cmax, ctx->cb_s,
-                               ctx->c_prev, ctx->drift_max, hp);
-            hipLaunchKernelGGL(k_cb_pairs<3>, gb, dim3(CB_THREADS), 0, st, (const float4 *)ctx->c32,
-                               (const TreeArgs *)ctx->trees, (const int32_t *)ctx->cb_chunk_cloud,
-                               (const int32_t *)ctx->cb_chunk_first, ctx->cb_s, hp);
-        }
+                               ctx->c_prev, ctx->drift_max, (const PairItem *)ctx->pair_items, ctx->B, ctx->tree_kcap, hp);
         return hip_ok(hipGetLastError(), "centroid tree launch") ? KM_OK : KM_ERR_HIP;
     }
     unsigned g = (unsigned)((k + 255) / 256);
@@ -584,7 +660,7 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
 // Allow the single-workgroup tree kernel its LDS budget.
 hipError_t tree_setup()
 {
-    int need = (int)small_tree_lds();
+    int need = (int)small_tree_lds(SMALL_K);
     (void)hipFuncSetAttribute((const void *)k_tree_small<2>, hipFuncAttributeMaxDynamicSharedMemorySize, need);
     (void)hipFuncSetAttribute((const void *)k_tree_small<3>, hipFuncAttributeMaxDynamicSharedMemorySize, need);
     (void)hipGetLastError(); // a refusal shows up as a launch error of the tree kernel instead

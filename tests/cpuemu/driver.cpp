@@ -14,6 +14,9 @@
 //   driver runb in.bin out.bin           (same input; one kmeans_run_batched
 //          call with the header's leaf_size and cand_tile = flags >> 20)
 //     out: int32 f, int32 G, assignment (n int32), centroids (k x d FP64)
+//   driver info in.bin out.bin / infob   (the input of kmeans / batched; the
+//          context is created and released)
+//     out: km_ctx_info
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -31,7 +34,7 @@ static void die(const char *what)
 int main(int argc, char **argv)
 {
     if (argc != 4) {
-        fprintf(stderr, "usage: driver kmeans|run|batched|runb in.bin out.bin\n");
+        fprintf(stderr, "usage: driver kmeans|run|batched|runb|info|infob in.bin out.bin\n");
         return 2;
     }
     FILE *f = fopen(argv[2], "rb");
@@ -41,7 +44,8 @@ int main(int argc, char **argv)
     if (fread(h, 8, 8, f) != 8)
         return 2;
     const int64_t n = h[0], d = h[1], k = h[2], iters = h[3];
-    const bool batched = !strcmp(argv[1], "batched") || !strcmp(argv[1], "runb");
+    const bool batched = !strcmp(argv[1], "batched") || !strcmp(argv[1], "runb") || !strcmp(argv[1], "infob");
+    const bool info = !strcmp(argv[1], "info") || !strcmp(argv[1], "infob");
     int64_t B = 1;
     std::vector<int64_t> pt_offs, c_offs;
     if (batched) {
@@ -88,7 +92,12 @@ int main(int argc, char **argv)
     } else if (kmeans_init(&ctx, &cfg, pts.data(), n, k, nullptr) != KM_OK)
         die("kmeans_init");
     FILE *o = fopen(argv[3], "wb");
-    if (!strcmp(argv[1], "kmeans") || batched) {
+    if (info) {
+        km_ctx_info ci;
+        if (kmeans_context_info(ctx, &ci) != KM_OK)
+            die("kmeans_context_info");
+        fwrite(&ci, sizeof(ci), 1, o);
+    } else if (!strcmp(argv[1], "kmeans") || batched) {
         std::vector<double> cn(k * d);
         for (int64_t t = 0; t < iters; ++t) {
             km_iter_stats st;

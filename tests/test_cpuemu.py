@@ -32,6 +32,10 @@ STATS = np.dtype([("n_changed", "<i8"), ("dist_evals", "<i8"), ("brute_evals", "
                   ("fallback_points", "<i8"), ("deferred_leaves", "<i8"), ("group_overflows", "<i8"),
                   ("groups_skipped", "<i8"), ("region_points", "<i8")])
 
+CTX_INFO = np.dtype([("device_bytes", "<i8"), ("model_bytes", "<i8"), ("model_bytes_actual_counts", "<i8"),
+                     ("leaves", "<i8"), ("groups", "<i8"), ("allocations", "<i8"), ("leaf_size", "<i4"),
+                     ("leaves_per_group", "<i4")])
+
 
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
@@ -51,6 +55,8 @@ def _run(driver, tmp_path, mode, x, c0, iters, algo, leaf_size=0, flags=0):
     r = subprocess.run([driver, mode, str(inp), str(out)], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, f"emulated run failed ({r.returncode}):\n{r.stderr[-4000:]}"
     raw = open(out, "rb").read()
+    if mode == "info":
+        return np.frombuffer(raw, CTX_INFO)[0]
     if mode == "run":
         it = int(np.frombuffer(raw[:4], np.int32)[0])
         a = np.frombuffer(raw[4:4 + 4 * n], np.int32)
@@ -117,7 +123,9 @@ KM_FLAG_SMALL_LISTS = 4
 
 def test_emulated_fallback_paths(driver, tmp_path):
     """Tiny candidate capacities: group overflow, deferred leaves and the
-    scan of all k centroids all run, and the trajectory is unchanged."""
+    scan of all k centroids all run, and the trajectory is unchanged.  The
+    statistics are folded by several workgroups that hand their totals to
+    the last one: the change counts and the objective still match."""
     x = geo_hotspots_2d(4000, n_hot=10, seed=81)
     c0 = init_centroids(x, 90, 82)
     ref = oracle.lloyd(x, c0, max_iter=3)
@@ -125,6 +133,9 @@ def test_emulated_fallback_paths(driver, tmp_path):
     for t, (a, c, st) in enumerate(got):
         np.testing.assert_array_equal(a, ref["a_hist"][t])
         np.testing.assert_array_equal(c, ref["c_hist"][t])
+        assert st["sse"] == pytest.approx(ref["sse"][t], rel=1e-12)
+        want = x.shape[0] if t == 0 else int((ref["a_hist"][t] != ref["a_hist"][t - 1]).sum())
+        assert st["n_changed"] == want
     tot = {f: sum(int(st[f]) for _, _, st in got) for f in ("group_overflows", "deferred_leaves", "fallback_points")}
     assert all(v > 0 for v in tot.values()), tot
 
@@ -176,6 +187,8 @@ def _run_batched(driver, tmp_path, mode, xs, cs, po, co, iters, leaf_size=0, can
     r = subprocess.run([driver, mode, str(inp), str(out)], capture_output=True, text=True, env=env, timeout=900)
     assert r.returncode == 0, f"emulated run failed ({r.returncode}):\n{r.stderr[-4000:]}"
     raw = open(out, "rb").read()
+    if mode == "infob":
+        return np.frombuffer(raw, CTX_INFO)[0]
     if mode == "runb":
         fG = np.frombuffer(raw[:8], np.int32)
         return (int(fG[0]), int(fG[1])), np.frombuffer(raw[8:8 + 4 * n], np.int32), \
@@ -219,3 +232,29 @@ def test_emulated_run_batched_autotune(driver, tmp_path):
     assert (f2, G2) == (32, 4)
     np.testing.assert_array_equal(a2, a)
     np.testing.assert_array_equal(c2, c)
+
+
+KM_FLAG_SMALL_LISTS, KM_FLAG_CELL_LEAVES = 4, 8
+
+
+@pytest.mark.parametrize("case", ["brute32", "brute32_20k", "brute64", "packed", "packed_f16", "cells",
+                                  "cells_20k", "small_lists", "tiny", "large_k", "batched"])
+def test_emulated_workspace_model_is_exact_with_actual_counts(driver, tmp_path, case):
+    """The workspace model evaluated with the context's actual leaf and group
+    counts equals the device bytes the context holds, on every path: each
+    buffer is allocated where the model puts it (no buffer of one part
+    takes the arena space of another)."""
+    if case == "batched":
+        xs, cs, po, co = _clouds([900, 40, 1300, 7, 600], [14, 40, 25, 1, 9], 97)
+        info = _run_batched(driver, tmp_path, "infob", xs, cs, po, co, 0)
+    else:
+        n, k = {"tiny": (300, 5), "large_k": (20000, 5000), "brute32_20k": (20000, 100),
+                "cells_20k": (20000, 100)}.get(case, (6000, 60))
+        x = geo_hotspots_2d(n, n_hot=12, seed=99).astype(np.float64 if case == "brute64" else np.float32)
+        c0 = init_centroids(x, k, 98)
+        algo = KM_BRUTE if case.startswith("brute") else KM_INDEXED
+        leaf = 16 if case == "packed_f16" else 0
+        flags = {"cells": KM_FLAG_CELL_LEAVES, "cells_20k": KM_FLAG_CELL_LEAVES,
+                 "small_lists": KM_FLAG_SMALL_LISTS}.get(case, 0)
+        info = _run(driver, tmp_path, "info", x, c0, 0, algo, leaf, flags)
+    assert info["model_bytes_actual_counts"] == info["device_bytes"], info
