@@ -253,8 +253,11 @@ static void fill_stats(const km_ctx *ctx, const int64_t *h, km_iter_stats *stats
 
 // One step's launches: A1 tree (+ inter bounds), A2-A5 assignment passes,
 // objective, refinement.  ev: KM_NPHASE + 1 events to record at the phase
-// boundaries, or null.
-static km_status step_body(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, hipEvent_t *ev)
+// boundaries, or null.  pos: the step's place in its sequence of launches
+// (a context's single steps, or the steps of one graph); the large-k
+// centroid tree re-sorts at every TREE_RESORT-th, the first included.
+static km_status step_body(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, hipEvent_t *ev,
+                           int64_t pos)
 {
     auto mark = [&](int i) {
         if (ev)
@@ -262,7 +265,7 @@ static km_status step_body(km_ctx *ctx, const double *c_in, double *c_out, int32
     };
     km_status s;
     mark(KM_PHASE_TREE);
-    if (ctx->cfg.point_dtype == KM_F32 && (s = build_centroid_tree(ctx, c_in)) != KM_OK)
+    if (ctx->cfg.point_dtype == KM_F32 && (s = build_centroid_tree(ctx, c_in, pos % TREE_RESORT == 0)) != KM_OK)
         return s;
     mark(KM_PHASE_ASSIGN);
     if ((s = run_assign(ctx, c_in, ev ? ev[KM_PHASE_DEFERRED] : nullptr)) != KM_OK)
@@ -281,11 +284,11 @@ static km_status step_body(km_ctx *ctx, const double *c_in, double *c_out, int32
 
 // A step with KM_FLAG_TIMING events when the context records them: the
 // step's events join the record only when the step succeeded.
-static km_status timed_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out)
+static km_status timed_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *assign_out, int64_t pos)
 {
     const bool timing = (ctx->cfg.flags & KM_FLAG_TIMING) != 0;
     if (!timing)
-        return step_body(ctx, c_in, c_out, assign_out, nullptr);
+        return step_body(ctx, c_in, c_out, assign_out, nullptr, pos);
     std::array<hipEvent_t, KM_NPHASE + 1> ev{};
     int have = 0;
     for (auto &e : ev) {
@@ -297,7 +300,7 @@ static km_status timed_step(km_ctx *ctx, const double *c_in, double *c_out, int3
         }
         ++have;
     }
-    km_status s = have == KM_NPHASE + 1 ? step_body(ctx, c_in, c_out, assign_out, ev.data()) : KM_ERR_HIP;
+    km_status s = have == KM_NPHASE + 1 ? step_body(ctx, c_in, c_out, assign_out, ev.data(), pos) : KM_ERR_HIP;
     if (s == KM_OK)
         ctx->ev_steps.push_back(ev);
     else
@@ -333,7 +336,7 @@ static bool chunk_graph(km_ctx *ctx, double *c)
     bool ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
         for (int i = 0; ok && i < RUN_CHUNK; ++i)
-            ok = step_body(ctx, c, c, nullptr, nullptr) == KM_OK;
+            ok = step_body(ctx, c, c, nullptr, nullptr, i) == KM_OK;
         ok = hipStreamEndCapture(ctx->cap_stream, &g) == hipSuccess && ok && g;
     }
     ctx->stream = saved;
@@ -599,8 +602,22 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
             no += (int)T.nnodes;
         }
         ctx->tree = ctx->h_trees[0];
+        // the large-k tree keeps its last order between sorts: start from the identity
+        std::vector<float4> order;
+        if (!small_trees(ctx)) {
+            order.resize((size_t)k);
+            for (int64_t j = 0; j < k; ++j) {
+                const int32_t id = (int32_t)j;
+                float w;
+                memcpy(&w, &id, sizeof(w)); // the id's bits, as the tree stores it
+                order[(size_t)j] = make_float4(0.0f, 0.0f, 0.0f, w);
+            }
+        }
         if (!hip_ok(hipMemcpyAsync(ctx->trees, ctx->h_trees.data(), B * sizeof(TreeArgs), hipMemcpyHostToDevice, st),
                     "hipMemcpyAsync") ||
+            (!order.empty() && !hip_ok(hipMemcpyAsync(cs, order.data(), order.size() * sizeof(float4),
+                                                      hipMemcpyHostToDevice, st),
+                                       "hipMemcpyAsync")) ||
             (!pairs.empty() && !hip_ok(hipMemcpyAsync(ctx->pair_items, pairs.data(), pairs.size() * sizeof(PairItem),
                                                       hipMemcpyHostToDevice, st),
                                        "hipMemcpyAsync")) ||
@@ -757,7 +774,7 @@ km_status kmeans_step(km_ctx *ctx, const double *c_in, double *c_out, int32_t *a
         set_error("kmeans_step: null argument");
         return KM_ERR_INVALID;
     }
-    km_status s = timed_step(ctx, c_in, c_out, assign_out);
+    km_status s = timed_step(ctx, c_in, c_out, assign_out, ctx->steps_done);
     if (s != KM_OK)
         return s;
     ctx->steps_done++;
@@ -827,7 +844,7 @@ km_status kmeans_run(km_ctx *ctx, double *c_inout, int32_t *assign_out, int32_t 
                 s = KM_ERR_HIP;
         } else {
             for (int i = 0; s == KM_OK && i < chunk; ++i)
-                s = timed_step(ctx, c, c, nullptr);
+                s = timed_step(ctx, c, c, nullptr, (int64_t)ctx->steps_done + launched + i);
         }
         launched += chunk;
         if (s != KM_OK || !stop_when_stable || launched >= max_iter)
@@ -902,7 +919,7 @@ static bool run_captured(km_ctx *ctx, double *c_inout, int32_t *assign_out, int3
     bool ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
         for (int i = 0; ok && i < iters; ++i)
-            ok = step_body(ctx, ctx->c_run, ctx->c_run, nullptr, nullptr) == KM_OK;
+            ok = step_body(ctx, ctx->c_run, ctx->c_run, nullptr, nullptr, i) == KM_OK;
         ok = hipStreamEndCapture(ctx->cap_stream, &g) == hipSuccess && ok && g;
     }
     ctx->stream = saved;

@@ -736,7 +736,8 @@ size_t scan_record_bytes(); // input-scan record per cloud (leaves.hip)
 km_status build_leaves(km_ctx *ctx, const void *points);
 
 // tree.hip
-km_status build_centroid_tree(km_ctx *ctx, const double *c_in);
+km_status build_centroid_tree(km_ctx *ctx, const double *c_in, bool resort);
+constexpr int TREE_RESORT = 8; // the centroid trees re-sort their centroids every this many steps
 bool small_trees(const km_ctx *ctx);
 constexpr int TREE_SMALL_K = 4096; // largest cloud whose tree one workgroup builds in LDS
 constexpr int PAIR_WAVES = 16;     // waves per pair-scan workgroup (the tree workgroup's size)

@@ -17,7 +17,6 @@
 namespace ekm {
 
 constexpr int SMALL_K = TREE_SMALL_K;
-constexpr int TREE_RESORT = 8; // the small-k tree re-sorts its centroids every this many steps
 constexpr int TREE_THREADS = 1024;
 constexpr int TREE_WAVES = TREE_THREADS / WAVE;
 
@@ -490,58 +489,198 @@ __global__ void __launch_bounds__(256) k_centroid_prep(const double *c, int64_t 
     }
 }
 
-// Inter bound of every centroid (large k): one thread per tree position,
-// nearest-neighbour search over the tree in global memory.
+// Inter bound of every centroid (large k): the smallest FP32 squared distance
+// from fl32(c_j) to another fl32 centroid (Eq. (3)), found with the tree.
+// One wave per 8 consecutive tree positions (a bucket; the last wave takes
+// the last 8, overlapping its neighbour, which computes the same values);
+// lane 8c + r works for centroid c of the 8 on slice r of the candidates.
+//  1. every centroid bounds its answer: by its distances to the other 7 of
+//     the wave, and from the previous step by Eq. (9) (nn_bound); S = the
+//     largest of these bounds;
+//  2. one descent keeps the nodes within some centroid's bound of it (box
+//     min-distance at most that bound; first tested for the wave's bounding
+//     box and S).  box_mind and bb_mind round like sqdist32 and are
+//     monotone, so they never exceed the FP32 distance to a member of the
+//     node: every node holding the nearest other centroid of one of the 8
+//     stays;
+//  3. the 8 lanes of a centroid scan the centroids of the surviving buckets,
+//     each lane every eighth, and their minima combine.
+// The minimum over those candidates is then the minimum over all centroids,
+// bit for bit.  If the frontier of a level outgrows fr_cap (NN_FR, or a few
+// entries with KM_FLAG_SMALL_LISTS to test this), every lane of the wave
+// searches on its own instead (nn_search, the same result).
+constexpr int NN_FR = 512; // frontier entries per wave and buffer
+constexpr int NN_WAVES = 4;
+constexpr int NN_GROUP = 8; // centroids per wave
 template <int D>
-__global__ void __launch_bounds__(256) k_centroid_nn(TreeArgs T, int64_t k, const unsigned *cmax_bits,
-                                                     const float *drift, const unsigned *drift_max, unsigned *cb_s,
-                                                     float *cb_hi, const int32_t *ctl)
+__global__ void __launch_bounds__(NN_WAVES * WAVE) k_centroid_nn(TreeArgs T, int64_t k, const unsigned *cmax_bits,
+                                                                const float *drift, const unsigned *drift_max,
+                                                                unsigned *cb_s, float *cb_hi, int fr_cap,
+                                                                const int32_t *ctl)
 {
+    static_assert(NN_GROUP * NN_GROUP == WAVE, "8 centroids x 8 slices per wave");
     if (ctl[CTL_STOP])
         return;
     const int have_prev = ctl[CTL_STEPS] > 0;
     __shared__ int64_t lev_size_sh[TREE_MAX_LEVELS], lev_off_sh[TREE_MAX_LEVELS];
+    __shared__ int32_t fr[NN_WAVES][2][NN_FR]; // fr_cap <= NN_FR of each buffer in use
     if (threadIdx.x < TREE_MAX_LEVELS) {
         lev_size_sh[threadIdx.x] = T.lev_size[threadIdx.x];
         lev_off_sh[threadIdx.x] = T.lev_off[threadIdx.x];
     }
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= k)
-        return;
+    const int lane = lane_id(), wid = (int)threadIdx.x / WAVE;
+    const int c = lane / NN_GROUP, r = lane % NN_GROUP;
+    int64_t w0 = ((int64_t)blockIdx.x * NN_WAVES + wid) * NN_GROUP;
+    if (w0 >= k)
+        return; // a whole wave past the end (k >= 8 on this path)
+    if (w0 + NN_GROUP > k)
+        w0 = k - NN_GROUP;
+    w0 = uniform_int((int)w0);
+    const int64_t t = w0 + c; // this lane's centroid (tree position)
     const float e = err_of(__uint_as_float(*cmax_bits));
     const float4 p = T.cs[t];
     const int j = __float_as_int(p.w);
     float cj[3] = {p.x, p.y, p.z};
-    auto cent = [&](int64_t q, float *o) {
-        const float4 v = T.cs[q];
-        o[0] = v.x;
-        o[1] = v.y;
-        o[2] = v.z;
-    };
-    auto box = [&](int l, int64_t i, float *lo, float *hi) {
-        const int64_t o = lev_off_sh[l] + i;
-        f4_to3(T.node_lo[o], lo);
-        f4_to3(T.node_hi[o], hi);
-    };
+    // 1. bounds: lane (c, r) measures centroid c against centroid r
+    float q[3];
+    for (int a = 0; a < 3; ++a)
+        q[a] = __shfl(cj[a], r * NN_GROUP); // centroid r sits in lanes 8r..8r+7
+    float u = r != c ? sqdist32<D>(cj, q) : INFINITY;
+    u = fminf(u, __shfl_xor(u, 1));
+    u = fminf(u, __shfl_xor(u, 2));
+    u = fminf(u, __shfl_xor(u, 4));
     const float s0 = nn_bound(have_prev != 0, have_prev ? cb_hi[j] : 0.0f, drift[j], __uint_as_float(*drift_max), e);
-    float sm = nn_search<D>(t, cj, s0, lev_size_sh, T.nlev, k, cent, box);
-    if (!(sm < s0) && s0 < INFINITY)
-        sm = nn_search<D>(t, cj, INFINITY, lev_size_sh, T.nlev, k, cent, box);
-    cb_s[j] = __float_as_uint(sm);
-    cb_hi[j] = dist_hi(sm, 2.0f * e); // the next step's search bound (Eq. (9))
+    const float bnd = fminf(u, s0);               // this centroid's bound
+    const float S = -wave_min_f32(-bnd);          // the largest bound of the 8
+    float blo[3], bhi[3];
+    for (int a = 0; a < 3; ++a) {
+        blo[a] = wave_min_f32(cj[a]);
+        bhi[a] = -wave_min_f32(-cj[a]);
+    }
+    // a node can hold the nearest other centroid of centroid g only if its
+    // box min-distance to c_g is at most g's bound (box_mind rounds like
+    // sqdist32 and is monotone too)
+    float gx[NN_GROUP][3], gb[NN_GROUP]; // the 8 centroids and their bounds, wave-uniform
+    for (int g = 0; g < NN_GROUP; ++g) {
+        for (int a = 0; a < 3; ++a)
+            gx[g][a] = rl_f(cj[a], NN_GROUP * g);
+        gb[g] = rl_f(bnd, NN_GROUP * g);
+    }
+    auto wanted = [&](const float *lo, const float *hi) {
+        if (bb_mind<D>(blo, bhi, lo, hi) > S)
+            return false;
+        bool any = false;
+        for (int g = 0; g < NN_GROUP; ++g)
+            any = any || box_mind<D>(lo, hi, gx[g]) <= gb[g];
+        return any;
+    };
+    // 2. descent from the root, keeping the wanted nodes
+    int32_t *cur = fr[wid][0], *nxt = fr[wid][1];
+    int ncur = 1;
+    if (lane == 0)
+        cur[0] = 0; // the root (level nlev - 1)
+    bool overflow = false;
+    for (int lev = T.nlev - 1; lev > 0 && !overflow; --lev) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t csz = lev_size_sh[lev - 1], coff = lev_off_sh[lev - 1];
+        int nnext = 0;
+        for (int c0 = 0; c0 < 8 * ncur; c0 += WAVE) {
+            const int ch = c0 + lane;
+            int64_t child = -1;
+            if (ch < 8 * ncur) {
+                const int64_t nd = 8 * (int64_t)cur[ch >> 3] + (ch & 7);
+                if (nd < csz) {
+                    float lo[3], hi[3];
+                    f4_to3(T.node_lo[coff + nd], lo);
+                    f4_to3(T.node_hi[coff + nd], hi);
+                    if (wanted(lo, hi))
+                        child = nd;
+                }
+            }
+            const uint64_t keep = __ballot(child >= 0);
+            const int at = nnext + __popcll(keep & lanemask_lt());
+            if (child >= 0 && at < fr_cap)
+                nxt[at] = (int32_t)child;
+            nnext += __popcll(keep);
+        }
+        nnext = uniform_int(nnext);
+        if (nnext > fr_cap)
+            overflow = true;
+        int32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        ncur = nnext;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float sm;
+    if (!overflow) {
+        // 3. lane (c, r): candidates r, r + 8, ... of the surviving buckets
+        float b0 = INFINITY, b1 = INFINITY;
+        const int ncand = 8 * ncur;
+        int m = r;
+        for (; m + NN_GROUP < ncand; m += 2 * NN_GROUP) {
+            const int64_t p0 = 8 * (int64_t)cur[m >> 3] + (m & 7);
+            const int64_t p1 = 8 * (int64_t)cur[(m + NN_GROUP) >> 3] + ((m + NN_GROUP) & 7);
+            if (p0 < k && p0 != t) {
+                float x[3];
+                f4_to3(T.cs[p0], x);
+                b0 = fminf(b0, sqdist32<D>(cj, x));
+            }
+            if (p1 < k && p1 != t) {
+                float x[3];
+                f4_to3(T.cs[p1], x);
+                b1 = fminf(b1, sqdist32<D>(cj, x));
+            }
+        }
+        if (m < ncand) {
+            const int64_t p0 = 8 * (int64_t)cur[m >> 3] + (m & 7);
+            if (p0 < k && p0 != t) {
+                float x[3];
+                f4_to3(T.cs[p0], x);
+                b0 = fminf(b0, sqdist32<D>(cj, x));
+            }
+        }
+        sm = fminf(b0, b1);
+        sm = fminf(sm, __shfl_xor(sm, 1));
+        sm = fminf(sm, __shfl_xor(sm, 2));
+        sm = fminf(sm, __shfl_xor(sm, 4));
+    } else {
+        auto cent = [&](int64_t qq, float *o) { f4_to3(T.cs[qq], o); };
+        auto box = [&](int l, int64_t i, float *lo, float *hi) {
+            const int64_t o = lev_off_sh[l] + i;
+            f4_to3(T.node_lo[o], lo);
+            f4_to3(T.node_hi[o], hi);
+        };
+        // bnd is attained (u) or bounds the answer (s0): the search returns
+        // min(bnd, the minimum), which is the minimum
+        sm = nn_search<D>(t, cj, bnd, lev_size_sh, T.nlev, k, cent, box);
+    }
+    if (r == 0) {
+        cb_s[j] = __float_as_uint(sm);
+        cb_hi[j] = dist_hi(sm, 2.0f * e); // the next step's search bound (Eq. (9))
+    }
 }
 
+// Buckets of the large-k tree: tree position t holds centroid sorted_id[t],
+// or, without a new sort (sorted_id null), the centroid it held in the last
+// build (its id in cs[t].w; the context starts with the identity order).
 __global__ void __launch_bounds__(256) k_tree_buckets(const float4 *c32, const int32_t *sorted_id, int64_t k,
-                                                      TreeArgs T)
+                                                      TreeArgs T, const int32_t *ctl)
 {
+    if (ctl[CTL_STOP])
+        return;
     int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= T.lev_size[0])
         return;
     float4 lo, hi;
     box_empty(lo, hi);
     for (int64_t t = b * TREE_BUCKET; t < k && t < (b + 1) * TREE_BUCKET; ++t) {
-        int id = sorted_id[t];
+        const int id = sorted_id ? sorted_id[t] : __float_as_int(T.cs[t].w);
         float4 p = c32[id];
         box_add(lo, hi, p);
         p.w = __int_as_float(id);
@@ -607,7 +746,10 @@ bool small_trees(const km_ctx *ctx)
     return true;
 }
 
-km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
+// resort: sort the large-k tree's centroids along the Morton curve (else
+// keep the last build's order; any order gives exact boxes, a stale one
+// only looser ones).  The small-k tree decides this on the device.
+km_status build_centroid_tree(km_ctx *ctx, const double *c_in, bool resort)
 {
     hipStream_t st = ctx->stream;
     const int64_t k = ctx->k;
@@ -627,7 +769,7 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
     }
     unsigned g = (unsigned)((k + 255) / 256);
     const bool indexed = ctx->cfg.algo == KM_INDEXED;
-    uint32_t *keys = indexed ? ctx->ckey : nullptr;
+    uint32_t *keys = indexed && resort ? ctx->ckey : nullptr;
     double *cprev = indexed ? ctx->c_prev : nullptr;
     if (ctx->d == 2)
         hipLaunchKernelGGL(k_centroid_prep<2>, dim3(g), dim3(256), 0, st, c_in, k, ctx->grid, ctx->c32, keys,
@@ -637,23 +779,29 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in)
                            ctx->cval, cmax, cprev, ctx->drift, ctx->drift_max, hp);
     if (!indexed) // the brute path needs only fl32(c) and the norm bound
         return hip_ok(hipGetLastError(), "centroid prep launch") ? KM_OK : KM_ERR_HIP;
-    bool in_tmp = false;
-    if (!hip_ok(radix_sort_u32(ctx->ckey, ctx->cval, ctx->ckey2, ctx->cval2, k, key_bits(ctx->d), ctx->rs_hist,
-                               ctx->scan_tmp, st, &in_tmp),
-                "centroid radix sort"))
-        return KM_ERR_HIP;
-    const int32_t *sid = in_tmp ? ctx->cval2 : ctx->cval;
+    const int32_t *sid = nullptr;
+    if (resort) {
+        bool in_tmp = false;
+        if (!hip_ok(radix_sort_u32(ctx->ckey, ctx->cval, ctx->ckey2, ctx->cval2, k, key_bits(ctx->d), ctx->rs_hist,
+                                   ctx->scan_tmp, st, &in_tmp),
+                    "centroid radix sort"))
+            return KM_ERR_HIP;
+        sid = in_tmp ? ctx->cval2 : ctx->cval;
+    }
     const TreeArgs &T = ctx->tree;
     hipLaunchKernelGGL(k_tree_buckets, dim3((unsigned)((T.lev_size[0] + 255) / 256)), dim3(256), 0, st, ctx->c32,
-                       sid, k, T);
+                       sid, k, T, hp);
     for (int l = 1; l < T.nlev; ++l)
         hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.lev_size[l] + 255) / 256)), dim3(256), 0, st, T, l);
+    const unsigned gnn = (unsigned)((k + NN_WAVES * NN_GROUP - 1) / (NN_WAVES * NN_GROUP));
     if (ctx->d == 2)
-        hipLaunchKernelGGL(k_centroid_nn<2>, dim3(g), dim3(256), 0, st, T, k, (const unsigned *)cmax,
-                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_s, ctx->cb_hi, hp);
+        hipLaunchKernelGGL(k_centroid_nn<2>, dim3(gnn), dim3(NN_WAVES * WAVE), 0, st, T, k, (const unsigned *)cmax,
+                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_s, ctx->cb_hi,
+                           ctx->small_lists ? 16 : NN_FR, hp);
     else
-        hipLaunchKernelGGL(k_centroid_nn<3>, dim3(g), dim3(256), 0, st, T, k, (const unsigned *)cmax,
-                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_s, ctx->cb_hi, hp);
+        hipLaunchKernelGGL(k_centroid_nn<3>, dim3(gnn), dim3(NN_WAVES * WAVE), 0, st, T, k, (const unsigned *)cmax,
+                           (const float *)ctx->drift, (const unsigned *)ctx->drift_max, ctx->cb_s, ctx->cb_hi,
+                           ctx->small_lists ? 16 : NN_FR, hp);
     return hip_ok(hipGetLastError(), "centroid tree launch") ? KM_OK : KM_ERR_HIP;
 }
 

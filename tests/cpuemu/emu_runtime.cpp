@@ -235,6 +235,15 @@ static bool resolve_wave(int w0, int w1)
             r = (src < nl && ((active >> src) & 1)) ? vals[src] : vals[me];
             break;
         }
+        case OP_SHFL: { // lane-indexed read (ds_bpermute); the source must be active
+            const int src = (int)L.a0 & 63;
+            if (src >= nl || !((active >> src) & 1)) {
+                fprintf(stderr, "cpuemu: __shfl from inactive lane %d\n", src);
+                abort();
+            }
+            r = vals[src];
+            break;
+        }
         case OP_WAVE_BARRIER:
             break;
         default:

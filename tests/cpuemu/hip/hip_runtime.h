@@ -53,7 +53,7 @@ extern dim3 g_block_dim, g_grid_dim;
 void *dyn_shared();
 
 // wave operations (all rendezvous over the live lanes of the wave)
-enum Op { OP_BALLOT = 1, OP_READLANE, OP_FIRSTLANE, OP_DPP, OP_SHFL_UP, OP_SHFL_XOR, OP_WAVE_BARRIER };
+enum Op { OP_BALLOT = 1, OP_READLANE, OP_FIRSTLANE, OP_DPP, OP_SHFL_UP, OP_SHFL_XOR, OP_WAVE_BARRIER, OP_SHFL };
 uint64_t wave_op(int op, uint64_t v, int64_t a0, int64_t a1, int64_t a2, const void *site);
 void block_barrier(const void *site);
 int lane();
@@ -119,6 +119,8 @@ template <class T>
 T __shfl_up(T v, unsigned delta) { return emu_shfl<T>(emu::OP_SHFL_UP, v, (int)delta); }
 template <class T>
 T __shfl_xor(T v, int mask) { return emu_shfl<T>(emu::OP_SHFL_XOR, v, mask); }
+template <class T>
+T __shfl(T v, int src) { return emu_shfl<T>(emu::OP_SHFL, v, src); }
 
 // bit casts and bit counts
 inline int __float_as_int(float f) { int i; memcpy(&i, &f, 4); return i; }

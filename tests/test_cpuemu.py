@@ -100,6 +100,29 @@ def test_emulated_indexed_3d(driver, tmp_path):
     _check(driver, tmp_path, x, c0, 3, KM_INDEXED)
 
 
+def test_emulated_large_k_tree_keeps_its_order(driver, tmp_path):
+    """k above the one-workgroup tree limit: the centroid tree is built in
+    global memory, sorted on the first step and every eighth after it, and
+    between sorts rebuilt over the order it had (and the inter bound comes
+    from the tree search seeded by the last step's bound plus drift).  Ten
+    steps equal the oracle's."""
+    x = ellipsoid_surfaces_3d(14000, 6, seed=75)
+    c0 = init_centroids(x, 4500, 76)
+    _check(driver, tmp_path, x, c0, 10, KM_INDEXED)
+
+
+def test_emulated_large_k_small_frontier(driver, tmp_path):
+    """The same path with tiny capacities: the wave search for the nearest
+    other centroid overflows its frontier and every lane searches alone."""
+    x = geo_hotspots_2d(4400, n_hot=15, seed=77).astype(np.float32)
+    c0 = init_centroids(x, 4150, 78)
+    ref = oracle.lloyd(x, c0, max_iter=2)
+    got = _run(driver, tmp_path, "kmeans", x, c0, 2, KM_INDEXED, 0, KM_FLAG_SSE | KM_FLAG_SMALL_LISTS)
+    for t, (a, c, st) in enumerate(got):
+        np.testing.assert_array_equal(a, ref["a_hist"][t])
+        np.testing.assert_array_equal(c, ref["c_hist"][t])
+
+
 def test_emulated_brute_fp32_and_fp64(driver, tmp_path):
     x = geo_hotspots_2d(1500, n_hot=6, seed=75)
     c0 = init_centroids(x, 20, 76)
