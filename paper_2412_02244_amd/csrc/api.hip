@@ -100,6 +100,7 @@ struct WsCounts {
     int64_t n = 0, k = 0, B = 1;
     int64_t L = 0, groups = 0;  // leaves, leaf groups
     int64_t nodes = 0, pair_blocks = 0; // centroid-tree nodes and inter-bound pair-scan workgroups
+    int64_t kmax = 0;                   // centroids of the largest cloud
 };
 
 // The workspace in the order the build allocates it: `build` (cloud tables,
@@ -135,7 +136,7 @@ static WsParts ws_parts(const km_config *cfg, const WsCounts &c)
                   al(c.pair_blocks * PAIR_WAVES, sizeof(PairItem)) +
                   3 * al(L, 4) + al(1, 4) + 3 * al(k, 4) + al(1, 4) + al(k * d, 8);
     p.rest += al(CTL_N, 4);
-    const int64_t nblk = indexed ? (c.groups + 3) / 4 + HEAVY_BLOCKS : (n + 255) / 256;
+    const int64_t nblk = indexed ? (c.groups + 3) / 4 + heavy_blocks(c.kmax) : (n + 255) / 256;
     if (leaf_state)
         p.groups = al(c.groups + 1, 4) + al(2 * c.groups, 16) + al(c.groups, 4);
     p.groups += al(nblk * NSTAT, 8);
@@ -170,6 +171,7 @@ static WsCounts ws_estimate(const km_config *cfg, int B, const int64_t *pt_off, 
         TreeArgs T;
         tree_layout(kb, T);
         c.nodes += T.nnodes;
+        c.kmax = kb > c.kmax ? kb : c.kmax;
         small = small && kb <= TREE_SMALL_K;
     }
     if (cfg->algo == KM_INDEXED && small)
@@ -514,6 +516,12 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
     ctx->tile = cfg->algo == KM_BRUTE && cfg->cand_tile ? cfg->cand_tile : 1024;
     ctx->stream = (hipStream_t)stream;
     ctx->small_lists = (cfg->flags & KM_FLAG_SMALL_LISTS) ? 1 : 0;
+    {
+        int64_t kmax = 0;
+        for (int b = 0; b < B; ++b)
+            kmax = c_off[b + 1] - c_off[b] > kmax ? c_off[b + 1] - c_off[b] : kmax;
+        ctx->heavy_wgs = heavy_blocks(kmax);
+    }
     hipGetDevice(&ctx->device);
     hipStream_t st = ctx->stream;
     km_status s;

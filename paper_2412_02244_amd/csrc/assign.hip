@@ -1038,10 +1038,74 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
 // same for every wave of the workgroup.
 struct HeavyShared {
     WaveHeavy ws;
-    uint64_t key[G_WAVES][WAVE];
+    uint64_t key[G_WAVES][WAVE]; // FP32 (value, id) keys; FP64 distance bits in the recheck
     float s2[G_WAVES][WAVE];
+    int32_t id64[G_WAVES][WAVE];
     int sn;
 };
+
+// FP32 best and second best of a point over centroids [j0, j1) of c32,
+// 64 at a time (the next chunk loaded while this one is scanned).
+template <int D>
+__device__ inline Best2 scan_range(const float (&x)[D], const AssignArgs &A, int64_t j0, int64_t j1)
+{
+    const int lane = lane_id();
+    Best2 bs[SCAN_ILP];
+#pragma unroll
+    for (int u = 0; u < SCAN_ILP; ++u)
+        bs[u] = best2_init();
+    float4 cur = j0 + lane < j1 ? A.c32[j0 + lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int64_t c = j0; c < j1; c += WAVE) {
+        const int64_t jn = c + WAVE + lane;
+        const float4 nxt = jn < j1 ? A.c32[jn] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const int cn = (int)(j1 - c < WAVE ? j1 - c : WAVE);
+        for (int b0 = 0; b0 < cn; b0 += SCAN_ILP) {
+#pragma unroll
+            for (int u = 0; u < SCAN_ILP; ++u) {
+                const int b = b0 + u;
+                if (b < cn) {
+                    float cc[3] = {rl_f(cur.x, b), rl_f(cur.y, b), D == 3 ? rl_f(cur.z, b) : 0.0f};
+                    best2_add(bs[u], sqdist32<D>(x, cc), (int)(c + b));
+                }
+            }
+        }
+        cur = nxt;
+    }
+#pragma unroll
+    for (int u = 1; u < SCAN_ILP; ++u)
+        bs[0] = best2_merge(bs[0], bs[u]);
+    return bs[0];
+}
+
+// The FP64 recheck over centroids [j0, j1): the canonical FP64 argmin
+// (value, lowest id) among the centroids whose FP32 distance is at most T
+// (every other one is strictly farther than the FP32 best, see lo_inverse),
+// for lanes with `re`.
+template <int D>
+__device__ inline void recheck_range(const float (&x)[D], bool re, float T, const AssignArgs &A, int64_t j0,
+                                     int64_t j1, double &bd, int &bj)
+{
+    const int lane = lane_id();
+    double xd[D];
+    for (int i = 0; i < D; ++i)
+        xd[i] = (double)x[i];
+    bd = INFINITY;
+    bj = 0x7fffffff;
+    for (int64_t c = j0; c < j1; c += WAVE) {
+        const float4 cur = c + lane < j1 ? A.c32[c + lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const int cn = (int)(j1 - c < WAVE ? j1 - c : WAVE);
+        for (int b = 0; b < cn; ++b) {
+            float cc[3] = {rl_f(cur.x, b), rl_f(cur.y, b), D == 3 ? rl_f(cur.z, b) : 0.0f};
+            if (re && sqdist32<D>(x, cc) <= T) {
+                const double Dv = sqdist64<D>(xd, A.c_in + (c + b) * D);
+                if (Dv < bd) { // ids increase: the lowest one wins a tie
+                    bd = Dv;
+                    bj = (int)(c + b);
+                }
+            }
+        }
+    }
+}
 
 template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
@@ -1088,13 +1152,55 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
                                  },
                                  st);
             }
-        } else if (w == 0) {
-            if (sn < 0 || m == 0) {
-                leaf_all<D>(A, J, e, Tp, st);
-            } else {
-                const LeafPts<D> P = load_pts<D>(A, J);
-                leaf_listed<D>(A, J, m, j1, thr, U, sn, e, hs.ws, P, st);
+        } else if (sn < 0 || m == 0) {
+            // no list: every point scans all of its cloud's centroids, each
+            // wave a quarter, FP32 first, then the FP64 recheck where the
+            // merged margin asks for it
+            const LeafPts<D> P = load_pts<D>(A, J);
+            const int64_t c0 = Tp->c0, kk = Tp->k;
+            const int64_t q0 = c0 + kk * w / G_WAVES, q1 = c0 + kk * (w + 1) / G_WAVES;
+            const Best2 b = scan_range<D>(P.x, A, q0, q1);
+            hs.key[w][lane] = b.key;
+            hs.s2[w][lane] = b.s2;
+            __syncthreads();
+            Best2 t = Best2{hs.key[0][lane], hs.s2[0][lane]};
+            for (int u = 1; u < G_WAVES; ++u)
+                t = best2_merge(t, Best2{hs.key[u][lane], hs.s2[u][lane]});
+            const float s1 = best2_s1(t);
+            const bool re = lane < J.size && !margin_safe(s1, t.s2, e);
+            __syncthreads(); // every wave has read the keys
+            int best64 = -1;
+            if (uniform_int(wave_count(re)) > 0) { // the same points in every wave
+                double bd;
+                int bj;
+                recheck_range<D>(P.x, re, lo_inverse(dist_hi(s1, e), e), A, q0, q1, bd, bj);
+                hs.key[w][lane] = (uint64_t)__double_as_longlong(bd); // non-negative: bits order like values
+                hs.id64[w][lane] = bj;
+                __syncthreads();
+                uint64_t kb = hs.key[0][lane];
+                int jb = hs.id64[0][lane];
+                for (int u = 1; u < G_WAVES; ++u) {
+                    const uint64_t ku = hs.key[u][lane];
+                    const int ju = hs.id64[u][lane];
+                    if (ku < kb || (ku == kb && ju < jb)) {
+                        kb = ku;
+                        jb = ju;
+                    }
+                }
+                best64 = jb;
             }
+            if (w == 0)
+                decide_points<D>(A, J, P, e, kk,
+                                 [&](const float (&x)[D], bool need, float &s1o) {
+                                     s1o = s1;
+                                     st[ST_RECHECK] += wave_count(need && re);
+                                     st[ST_FALLBACK_PTS] += wave_count(need);
+                                     return re ? best64 : best2_id(t);
+                                 },
+                                 st);
+        } else if (w == 0) {
+            const LeafPts<D> P = load_pts<D>(A, J);
+            leaf_listed<D>(A, J, m, j1, thr, U, sn, e, hs.ws, P, st);
         }
 #pragma unroll
         for (int q = 0; q < NSTAT; ++q)
@@ -1343,7 +1449,7 @@ int64_t assign_grid(km_ctx *ctx) { return (ctx->ngroups + G_WAVES - 1) / G_WAVES
 int64_t assign_blocks(km_ctx *ctx)
 {
     if (ctx->cfg.algo == KM_INDEXED)
-        return assign_grid(ctx) + HEAVY_BLOCKS;
+        return assign_grid(ctx) + ctx->heavy_wgs;
     return (ctx->n + ASSIGN_THREADS - 1) / ASSIGN_THREADS;
 }
 
@@ -1357,7 +1463,7 @@ km_status run_assign(km_ctx *ctx, const double *c_in, hipEvent_t between)
     const unsigned nwg = ctx->cfg.algo == KM_INDEXED ? (unsigned)assign_grid(ctx) : 0u;
     const int D = ctx->d;
     if (ctx->cfg.algo == KM_INDEXED) {
-        const unsigned nhw = (unsigned)HEAVY_BLOCKS;
+        const unsigned nhw = (unsigned)ctx->heavy_wgs;
         if (D == 2)
             hipLaunchKernelGGL(k_assign_waves<2>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
         else

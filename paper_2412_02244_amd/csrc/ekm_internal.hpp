@@ -24,9 +24,12 @@ constexpr int DEFAULT_G_2D = 6;  // default leaves per group in 2D (3D: GROUP_LE
 // are deferred (measured: deferring crowded leaves cost more in the extra
 // pass than it saved in the main one); the small-list test mode lowers it.
 constexpr int HEAVY_M = 256;
-// Workgroups of the per-leaf pass (one per CU): workgroup b takes the
-// deferred leaves b, b + HEAVY_BLOCKS, ... of the step's list.
-constexpr int HEAVY_BLOCKS = 64;
+// Workgroups of the per-leaf pass (one per CU): workgroup b of W takes the
+// deferred leaves b, b + W, ... of the step's list.  Many leaves are
+// deferred only with many centroids per cloud (crowded candidate lists):
+// then every CU takes part; otherwise a quarter of them, which keeps the
+// usually empty pass short.
+inline int heavy_blocks(int64_t kmax) { return kmax >= 8192 ? 256 : 64; }
 constexpr int TREE_BUCKET = 8;   // centroids per centroid-tree leaf bucket
 constexpr int TREE_MAX_LEVELS = 8;
 constexpr int TREE_START_MAX = 512; // nodes a descent evaluates at its first level
@@ -583,6 +586,7 @@ struct km_ctx {
     int64_t npair_blocks = 0;
     ekm::PairItem *pair_items = nullptr;
     int tree_kcap = 64;              // LDS capacity of the small-k tree launch (small_tree_cap)
+    int heavy_wgs = 64;              // workgroups of the per-leaf pass (heavy_blocks of the largest cloud)
     int tile = 1024;     // brute-path LDS tile (centroids)
     int S = 0;           // fixed-point scale exponent
     int fix64 = 0;       // every point's fixed-point coordinate fits FIX64_BITS bits

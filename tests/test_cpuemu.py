@@ -163,6 +163,26 @@ def test_emulated_fallback_paths(driver, tmp_path):
     assert all(v > 0 for v in tot.values()), tot
 
 
+def test_emulated_fallback_scan_with_fp32_blind_ties(driver, tmp_path):
+    """Centroid pairs that FP32 cannot tell apart (their fl32 copies are
+    equal; FP64 makes the higher index nearer for some points), with tiny
+    list capacities: leaves scan all k centroids, and the FP64 recheck of
+    that scan gives the oracle's lowest-index FP64 argmin."""
+    rng = np.random.default_rng(83)
+    base = rng.uniform(0.25, 0.75, (24, 2)).astype(np.float32).astype(np.float64)
+    c0 = np.empty((48, 2))
+    c0[0::2] = base + np.array([3e-9, 0.0])  # below half an FP32 ulp: the same fl32 point
+    c0[1::2] = base
+    x = (np.repeat(base, 40, 0) + rng.normal(0, 0.01, (40 * base.shape[0], 2))).astype(np.float32)
+    ref = oracle.lloyd(x, c0, max_iter=2)
+    assert (ref["a_hist"][0] % 2 == 1).any() and (ref["a_hist"][0] % 2 == 0).any()
+    got = _run(driver, tmp_path, "kmeans", x, c0, 2, KM_INDEXED, 0, KM_FLAG_SSE | KM_FLAG_SMALL_LISTS)
+    for t, (a, c, st) in enumerate(got):
+        np.testing.assert_array_equal(a, ref["a_hist"][t])
+        np.testing.assert_array_equal(c, ref["c_hist"][t])
+    assert got[0][2]["rechecked"] > 0 and got[0][2]["fallback_points"] > 0, got[0][2]
+
+
 def test_emulated_long_trajectory_inter_bounds(driver, tmp_path):
     """Ten steps: the exact sums are carried from step to step and moved
     point by point or leaf by leaf, the inter bounds keep leaves and points,

@@ -173,6 +173,10 @@ def test_fp32_blind_near_ties_are_rechecked(ekm):
     for algo in (ekm.KM_INDEXED, ekm.KM_BRUTE):
         stats = _compare(ekm, x, c0, ref, f"fp32-blind ties algo={algo}", algo=algo)
         assert stats[0]["rechecked"] > 0
+    # tiny lists: leaves scan all k (split over a workgroup's waves) and the
+    # recheck runs there too
+    stats = _compare(ekm, x, c0, ref, "fp32-blind ties, small lists", flags=ekm.KM_FLAG_SMALL_LISTS)
+    assert stats[0]["rechecked"] > 0 and sum(s["fallback_points"] for s in stats) > 0
 
 
 def test_large_offset_data(ekm):
