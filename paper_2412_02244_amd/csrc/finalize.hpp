@@ -9,8 +9,8 @@ namespace ekm {
 constexpr int FIN_THREADS = 256;
 
 struct FinShared {
-    long long red[NSTAT][FIN_THREADS];
-    double dred[FIN_THREADS];
+    long long red[NSTAT][FIN_THREADS / WAVE]; // per-wave totals
+    double dred[FIN_THREADS / WAVE];
     int last;
 };
 
@@ -71,7 +71,7 @@ struct FinStats {
 // The step's statistics, folded by F.nwg workgroups of FIN_THREADS threads
 // (w = 0 .. nwg - 1).  Workgroup w folds rows [w R, (w + 1) R) of the
 // per-block partials (and the same share of the objective partials), each
-// thread whole rows, then a fixed-shape tree combines its threads.  With
+// thread whole rows, then its threads are combined in a fixed order.  With
 // several workgroups, each writes its totals, and the last one to finish
 // (a ticket counter) adds them up in workgroup order.  Integer counters
 // are exact in any order and the objective is summed in a fixed order, so
@@ -99,18 +99,30 @@ __device__ inline void fin_stats(FinShared &fs, const FinStats &F, int64_t w)
     double s = 0.0;
     for (int64_t b = w * Rs + threadIdx.x; b < s1; b += FIN_THREADS)
         s += F.sse_part[b];
-    for (int q = 0; q < NSTAT; ++q)
-        fs.red[q][threadIdx.x] = acc8[q];
-    fs.dred[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            for (int q = 0; q < NSTAT; ++q)
-                fs.red[q][threadIdx.x] += fs.red[q][threadIdx.x + o];
-            fs.dred[threadIdx.x] += fs.dred[threadIdx.x + o];
-        }
-        __syncthreads();
+    // each wave sums its lanes (a fixed order), then thread q adds the wave
+    // totals of value q in wave order
+    const int wv = (int)threadIdx.x / WAVE;
+    for (int q = 0; q < NSTAT; ++q) {
+        const int64_t v = wave_sum_i64(acc8[q]);
+        if (lane_id() == 0)
+            fs.red[q][wv] = v;
     }
+    const double dv = wave_sum_f64(s);
+    if (lane_id() == 0)
+        fs.dred[wv] = dv;
+    __syncthreads();
+    if (threadIdx.x < NSTAT) {
+        long long t = fs.red[threadIdx.x][0];
+        for (int u = 1; u < FIN_THREADS / WAVE; ++u)
+            t += fs.red[threadIdx.x][u];
+        fs.red[threadIdx.x][0] = t;
+    } else if (threadIdx.x == NSTAT) {
+        double d = fs.dred[0];
+        for (int u = 1; u < FIN_THREADS / WAVE; ++u)
+            d += fs.dred[u];
+        fs.dred[0] = d;
+    }
+    __syncthreads();
     if (F.nwg > 1) {
         // hand this workgroup's totals over; the last workgroup folds them
         if (threadIdx.x < NSTAT)

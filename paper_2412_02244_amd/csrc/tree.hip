@@ -233,7 +233,7 @@ __device__ void pair_block(const double *c_all, const PairItem *items, unsigned 
 // s * PAIR_SCAN >= k_b (at most PAIR_WAVES), so a wave scans about
 // PAIR_SCAN centroids; the s waves of a chunk start at a multiple of s and
 // therefore share a workgroup.  Unused waves are idle (first = -1).
-constexpr int PAIR_SCAN = 128;
+constexpr int PAIR_SCAN = 64;
 int64_t pair_plan(const int64_t *c_off, int B, std::vector<PairItem> *items)
 {
     int64_t pos = 0; // waves placed
