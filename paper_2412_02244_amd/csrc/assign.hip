@@ -1110,8 +1110,8 @@ __device__ inline void recheck_range(const float (&x)[D], bool re, float T, cons
 template <int D>
 __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_heavy(AssignArgs A)
 {
-    if (A.ctl[CTL_STOP])
-        return; // the run is over (the whole workgroup returns)
+    if (A.ctl[CTL_STOP] || *A.heavy_cnt == 0)
+        return; // the run is over, or no leaf was deferred (the finalize kernel then skips these rows)
     __shared__ HeavyShared hs;
     __shared__ BlockCombine bc;
     combine_init(bc);

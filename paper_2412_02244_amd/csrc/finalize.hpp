@@ -52,6 +52,7 @@ inline int64_t fin_stat_wgs(int64_t nblk, int rows)
 
 struct FinStats {
     int64_t nblk;               // rows of per-block counters
+    int64_t nheavy;             // the last rows belong to the per-leaf pass: skipped when it had no leaf
     const int64_t *stat_part;   // [nblk][NSTAT]
     int64_t nsse;               // objective partials (0: none)
     const double *sse_part;
@@ -80,8 +81,11 @@ struct FinStats {
 // t >= 2 whose assignment equals that of step t - 1.
 __device__ inline void fin_stats(FinShared &fs, const FinStats &F, int64_t w)
 {
-    const int64_t R = (F.nblk + F.nwg - 1) / F.nwg, Rs = (F.nsse + F.nwg - 1) / F.nwg;
-    const int64_t r1 = (w + 1) * R < F.nblk ? (w + 1) * R : F.nblk;
+    // the per-leaf pass writes its rows only when it had leaves (the count
+    // is read before the last workgroup clears it)
+    const int64_t nrows = F.heavy_cnt && *F.heavy_cnt == 0 ? F.nblk - F.nheavy : F.nblk;
+    const int64_t R = (nrows + F.nwg - 1) / F.nwg, Rs = (F.nsse + F.nwg - 1) / F.nwg;
+    const int64_t r1 = (w + 1) * R < nrows ? (w + 1) * R : nrows;
     const int64_t s1 = (w + 1) * Rs < F.nsse ? (w + 1) * Rs : F.nsse;
     long long acc8[NSTAT];
     for (int q = 0; q < NSTAT; ++q)

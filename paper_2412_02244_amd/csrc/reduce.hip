@@ -56,6 +56,7 @@ FinStats fin_stats_args(km_ctx *ctx, bool with_sse)
 {
     FinStats F;
     F.nblk = assign_blocks(ctx);
+    F.nheavy = ctx->cfg.algo == KM_INDEXED ? ctx->heavy_wgs : 0;
     F.stat_part = ctx->stat_part;
     F.nsse = with_sse ? ctx->nblk_sse : 0;
     F.sse_part = ctx->sse_part;
