@@ -160,28 +160,63 @@ __global__ void __launch_bounds__(DT_THREADS) k_dist_zero(int64_t *acc, int64_t 
 }
 
 template <class T>
+__device__ inline void window_add(T t, int &ne, int &em, int &any)
+{
+    if (t != (T)0) {
+        int el, eh;
+        if (sizeof(T) == 4)
+            bits_f32((float)t, el, eh);
+        else
+            bits_f64((double)t, el, eh);
+        ne = max(ne, -el);
+        em = max(em, eh);
+        any = 1;
+    }
+}
+
+// Four independent loads per thread and round; one lane per workgroup takes
+// part in the atomics.
+template <class T>
 __global__ void __launch_bounds__(DT_THREADS) k_dist_window(const T *v, int64_t m, const T *w, int64_t mw,
                                                             WinOut *out)
 {
     int ne = -100000, em = -100000, any = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m + mw; q += stride) {
-        T t = q < m ? v[q] : w[q - m];
-        if (t != (T)0) {
-            int el, eh;
-            if (sizeof(T) == 4)
-                bits_f32((float)t, el, eh);
-            else
-                bits_f64((double)t, el, eh);
-            ne = max(ne, -el);
-            em = max(em, eh);
-            any = 1;
-        }
+    const int64_t tot = m + mw, stride = (int64_t)gridDim.x * blockDim.x;
+    auto at = [&](int64_t q) { return q < m ? v[q] : w[q - m]; };
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; q + 3 * stride < tot; q += 4 * stride) {
+        const T t0 = at(q), t1 = at(q + stride), t2 = at(q + 2 * stride), t3 = at(q + 3 * stride);
+        window_add(t0, ne, em, any);
+        window_add(t1, ne, em, any);
+        window_add(t2, ne, em, any);
+        window_add(t3, ne, em, any);
     }
-    if (any) {
-        atomicMax(&out->neg_elsb, ne);
-        atomicMax(&out->emsb, em);
-        atomicOr(&out->any, 1);
+    for (; q < tot; q += stride)
+        window_add(at(q), ne, em, any);
+    for (int o = 1; o < WAVE; o <<= 1) {
+        ne = max(ne, __shfl_xor(ne, o));
+        em = max(em, __shfl_xor(em, o));
+        any |= __shfl_xor(any, o);
+    }
+    __shared__ int red[3][DT_THREADS / WAVE];
+    const int wv = (int)threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        red[0][wv] = ne;
+        red[1][wv] = em;
+        red[2][wv] = any;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int u = 1; u < DT_THREADS / WAVE; ++u) {
+            ne = max(ne, red[0][u]);
+            em = max(em, red[1][u]);
+            any |= red[2][u];
+        }
+        if (any) {
+            atomicMax(&out->neg_elsb, ne);
+            atomicMax(&out->emsb, em);
+            atomicOr(&out->any, 1);
+        }
     }
 }
 
@@ -212,8 +247,61 @@ __global__ void __launch_bounds__(DT_THREADS) k_dist_acc(const T *x, const int32
         else
             fix_split_f64((double)v, S, hi[i], lo[i]);
     }
-    wave_accumulate<D>(valid, j, hi, lo, acc + b * k * D * 2, cnt + b * k);
+    // points in caller order fall into many clusters per wave: at most two
+    // wave reductions, then per-lane atomics
+    wave_accumulate_few<D>(valid, j, hi, lo, acc + b * k * D * 2, cnt + b * k, 2);
 }
+
+// The same sums with the clusters of one cloud in LDS: workgroup (x, b)
+// adds points [x P, (x + 1) P) of cloud b with LDS atomics, then adds its
+// non-zero partial sums to the global ones (integer sums: exact in any
+// order).  LDS: k (2 D) int64 and k int32.
+constexpr int DT_LDS_THREADS = 1024;
+constexpr int64_t DT_LDS_POINTS = 16384; // points per workgroup
+template <class T, int D>
+__global__ void __launch_bounds__(DT_LDS_THREADS) k_dist_acc_lds(const T *x, const int32_t *a, int64_t n, int64_t k,
+                                                                 const WinOut *win, int logn, int64_t *acc,
+                                                                 int32_t *cnt)
+{
+    int S;
+    if (!window_ok(*win, logn, S))
+        return; // k_dist_gc reports it (the whole workgroup returns)
+    extern __shared__ int64_t sacc[]; // [k][D][2], then [k] int32 counts
+    int32_t *scnt = (int32_t *)(sacc + k * D * 2);
+    const int64_t b = blockIdx.y;
+    for (int64_t q = threadIdx.x; q < k * D * 2; q += blockDim.x)
+        sacc[q] = 0;
+    for (int64_t q = threadIdx.x; q < k; q += blockDim.x)
+        scnt[q] = 0;
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * DT_LDS_POINTS;
+    const int64_t p1 = p0 + DT_LDS_POINTS < n ? p0 + DT_LDS_POINTS : n;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int j = a[b * n + p];
+        for (int i = 0; i < D; ++i) {
+            int64_t hi, lo;
+            const T v = x[(b * n + p) * D + i];
+            if (sizeof(T) == 4)
+                fix_split_f32((float)v, S, hi, lo);
+            else
+                fix_split_f64((double)v, S, hi, lo);
+            atomicAdd((unsigned long long *)&sacc[((int64_t)j * D + i) * 2], (unsigned long long)hi);
+            atomicAdd((unsigned long long *)&sacc[((int64_t)j * D + i) * 2 + 1], (unsigned long long)lo);
+        }
+        atomicAdd(&scnt[j], 1);
+    }
+    __syncthreads();
+    int64_t *ab = acc + b * k * D * 2;
+    int32_t *cb = cnt + b * k;
+    for (int64_t q = threadIdx.x; q < k * D * 2; q += blockDim.x)
+        if (sacc[q])
+            atomicAdd((unsigned long long *)&ab[q], (unsigned long long)sacc[q]);
+    for (int64_t q = threadIdx.x; q < k; q += blockDim.x)
+        if (scnt[q])
+            atomicAdd(&cb[q], scnt[q]);
+}
+static size_t dist_acc_lds_bytes(int64_t k, int d) { return (size_t)k * d * 2 * 8 + (size_t)k * 4; }
+constexpr size_t DT_LDS_MAX = 64 * 1024; // clusters of a cloud kept in LDS up to this size
 
 template <class T, int D>
 __global__ void __launch_bounds__(DT_THREADS) k_dist_gc(const T *c, const double *g, int64_t B, int64_t k,
@@ -313,10 +401,21 @@ static km_status bwd_t(const T *x, const T *c, const int32_t *a, const double *g
     unsigned zb = (unsigned)((nacc + DT_THREADS - 1) / DT_THREADS);
     zb = zb < 1 ? 1 : (zb > 4096 ? 4096 : zb);
     hipLaunchKernelGGL(k_dist_zero, dim3(zb), dim3(DT_THREADS), 0, st, acc, nacc, cnt, ncnt, win);
-    hipLaunchKernelGGL(k_dist_window<T>, dim3(1024), dim3(DT_THREADS), 0, st, x, B * n * D, c, B * k * D, win);
-    dim3 grid((unsigned)((n + DT_THREADS - 1) / DT_THREADS), (unsigned)B);
-    hipLaunchKernelGGL((k_dist_acc<T, D>), grid, dim3(DT_THREADS), 0, st, x, a, n, k, (const WinOut *)win, logn, acc,
-                       cnt);
+    const int64_t nwin = B * n * D + B * k * D;
+    int64_t wb = (nwin + 4 * DT_THREADS - 1) / (4 * DT_THREADS);
+    wb = wb < 1 ? 1 : (wb > 1024 ? 1024 : wb); // few workgroups: their atomics meet on three words
+    hipLaunchKernelGGL(k_dist_window<T>, dim3((unsigned)wb), dim3(DT_THREADS), 0, st, x, B * n * D, c, B * k * D,
+                       win);
+    const size_t lds = dist_acc_lds_bytes(k, D);
+    if (lds <= DT_LDS_MAX) {
+        dim3 grid((unsigned)((n + DT_LDS_POINTS - 1) / DT_LDS_POINTS), (unsigned)B);
+        hipLaunchKernelGGL((k_dist_acc_lds<T, D>), grid, dim3(DT_LDS_THREADS), lds, st, x, a, n, k,
+                           (const WinOut *)win, logn, acc, cnt);
+    } else {
+        dim3 grid((unsigned)((n + DT_THREADS - 1) / DT_THREADS), (unsigned)B);
+        hipLaunchKernelGGL((k_dist_acc<T, D>), grid, dim3(DT_THREADS), 0, st, x, a, n, k, (const WinOut *)win, logn,
+                           acc, cnt);
+    }
     const int64_t tot = B * k;
     hipLaunchKernelGGL((k_dist_gc<T, D>), dim3((unsigned)((tot + DT_THREADS - 1) / DT_THREADS)), dim3(DT_THREADS), 0,
                        st, c, g, B, k, win, logn, (const int64_t *)acc, (const int32_t *)cnt, gc);

@@ -515,6 +515,48 @@ __device__ inline void wave_accumulate(bool valid, int a, const int64_t (&hi)[D]
     }
 }
 
+// As wave_accumulate for at most `groups` clusters of the wave; the lanes of
+// any further cluster add their own values (per-lane integer atomics, the
+// same exact sums).  For points spread over many clusters the wave
+// reductions would cost more than the atomics they save.
+template <int D>
+__device__ inline void wave_accumulate_few(bool valid, int a, const int64_t (&hi)[D], const int64_t (&lo)[D],
+                                           int64_t *acc, int32_t *cnt, int groups)
+{
+    uint64_t active = __ballot(valid);
+    for (int g = 0; active && g < groups; ++g) {
+        const int leader = __ffsll((unsigned long long)active) - 1;
+        const int c = rl_i(a, leader);
+        const bool in = valid && a == c && ((active >> lane_id()) & 1ull);
+        const uint64_t grp = __ballot(in);
+        int64_t sh[D], sl[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            sh[i] = wave_sum_i64(in ? hi[i] : 0);
+            sl[i] = wave_sum_i64(in ? lo[i] : 0);
+        }
+        if (lane_id() == leader) {
+            int64_t *ac = acc + (int64_t)c * D * 2;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                atomicAdd((unsigned long long *)&ac[2 * i], (unsigned long long)sh[i]);
+                atomicAdd((unsigned long long *)&ac[2 * i + 1], (unsigned long long)sl[i]);
+            }
+            atomicAdd(&cnt[c], (int32_t)__popcll(grp));
+        }
+        active &= ~grp;
+    }
+    if ((active >> lane_id()) & 1ull) {
+        int64_t *ac = acc + (int64_t)a * D * 2;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            atomicAdd((unsigned long long *)&ac[2 * i], (unsigned long long)hi[i]);
+            atomicAdd((unsigned long long *)&ac[2 * i + 1], (unsigned long long)lo[i]);
+        }
+        atomicAdd(&cnt[a], 1);
+    }
+}
+
 // Cloud of point (or sorted position) i: the b with off[b] <= i < off[b + 1]
 // (every cloud is non-empty).
 __device__ inline int cloud_of(const int64_t *off, int B, int64_t i)
