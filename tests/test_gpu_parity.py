@@ -260,11 +260,15 @@ def test_deterministic_stats(ekm):
         assert s1 == s2
 
 
+@pytest.mark.parametrize("k", [40, 1500])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_distortion_fwd_bwd(ekm, dtype):
+def test_distortion_fwd_bwd(ekm, dtype, k):
+    """k = 40: the centroid-gradient sums of a cloud sit in LDS, and the
+    20,000 points of a cloud span two LDS workgroups; k = 1500 (3D): they do
+    not fit, and the kernel with global atomics runs."""
     import torch
     from synth import distortion_batch
-    xb, cb = distortion_batch(n_clouds=4, n=3000, k=40, seed=51)
+    xb, cb = distortion_batch(n_clouds=4, n=20_000 if k == 40 else 5000, k=k, seed=51)
     if dtype == "f64":
         xb, cb = xb.astype(np.float64), cb.astype(np.float64)
     dev = torch.device("cuda:0")
