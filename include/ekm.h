@@ -267,9 +267,10 @@ EKM_API km_status kmeans_init_batched(km_ctx **out, const km_config *cfg, const 
  * and launched once, the assignment is written and the workspace released.
  *   c_inout:    device, k x d FP64 (all clouds' centroids), refined in place.
  *   assign_out: device, n int32 (cloud-local ids, caller order), or NULL.
- *   cfg->leaf_size == 0 / cfg->cand_tile == 0: chosen by timing a few
- *   iterations of each candidate (leaf sizes 16, 32, 64; 4, 6 or 8 leaves
- *   per candidate list) on up to 64 evenly spaced clouds; the choice is cached
+ *   cfg->leaf_size == 0 / cfg->cand_tile == 0: chosen by timing iterations
+ *   2..9 (one captured graph of 8 steps) of each candidate (leaf sizes 16,
+ *   32, 64; 4, 6 or 8 leaves per candidate list) on evenly spaced clouds
+ *   (all of them up to 64, else max(64, B / 8)); the choice is cached
  *   per GPU architecture and workload class (d, typical cloud size and
  *   centroid count) for the rest of the process.
  *   tuned_out:  host int32[2] receiving the leaf size and the leaves per

@@ -1001,8 +1001,10 @@ static km_status autotune(const km_config *cfg, const void *points, const int64_
             return KM_OK;
         }
     }
-    // the sample: clouds floor(i B / S), copied into their own arrays
-    const int S = B < 64 ? B : 64;
+    // the sample: clouds floor(i B / S), copied into their own arrays; at
+    // least 64 clouds and an eighth of them, so that the candidates' run
+    // times are not buried under the fixed cost of each launch
+    const int S = B <= 64 ? B : (B / 8 > 64 ? B / 8 : 64);
     const int d = cfg->d;
     std::vector<int64_t> spt(S + 1, 0), sco(S + 1, 0);
     std::vector<int> pick(S);
@@ -1060,7 +1062,7 @@ static km_status autotune(const km_config *cfg, const void *points, const int64_
                         "autotune: copy") ||
                 (s = kmeans_run(ctx, ct, nullptr, 1, 0, nullptr, nullptr)) != KM_OK ||
                 !hip_ok(hipEventRecord(e0, st), "autotune: hipEventRecord") ||
-                (s = kmeans_run(ctx, ct, nullptr, 3, 0, nullptr, nullptr)) != KM_OK ||
+                (s = kmeans_run(ctx, ct, nullptr, RUN_CHUNK, 0, nullptr, nullptr)) != KM_OK ||
                 !hip_ok(hipEventRecord(e1, st), "autotune: hipEventRecord") ||
                 !hip_ok(hipEventSynchronize(e1), "autotune: hipEventSynchronize") ||
                 !hip_ok(hipEventElapsedTime(&ms, e0, e1), "autotune: hipEventElapsedTime"))
