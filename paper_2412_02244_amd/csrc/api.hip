@@ -138,7 +138,7 @@ static WsParts ws_parts(const km_config *cfg, const WsCounts &c)
     p.rest += al(CTL_N, 4);
     const int64_t nblk = indexed ? (c.groups + 3) / 4 + heavy_blocks(c.kmax) : (n + 255) / 256;
     if (leaf_state)
-        p.groups = al(c.groups + 1, 4) + al(2 * c.groups, 16) + al(c.groups, 4);
+        p.groups = al(c.groups + 1, 4) + al(2 * c.groups, 16) + 2 * al(c.groups, 4);
     p.groups += al(nblk * NSTAT, 8);
     p.hist = (size_t)HIST_ROWS * (NSTAT + 1) * 8;
     return p;
@@ -642,8 +642,9 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
         ctx->drift = ctx_alloc<float>(ctx, k);
         ctx->drift_max = ctx_alloc<unsigned>(ctx, 1);
         ctx->c_prev = ctx_alloc<double>(ctx, (size_t)k * ctx->d);
+        ctx->group_parts = ctx_alloc_groups<int32_t>(ctx, ctx->ngroups);
         if (!ctx->leaf_own || !ctx->leaf_r || !ctx->heavy || !ctx->heavy_cnt || !ctx->cb_s ||
-            !ctx->cb_hi || !ctx->drift || !ctx->drift_max || !ctx->c_prev) {
+            !ctx->cb_hi || !ctx->drift || !ctx->drift_max || !ctx->c_prev || !ctx->group_parts) {
             kmeans_destroy(ctx);
             return alloc_fail(nullptr);
         }
@@ -651,7 +652,8 @@ static km_status init_context(km_ctx **out, const km_config *cfg, const void *po
             !hip_ok(hipMemsetD32Async(ctx->leaf_r, 0x7f800000, L, st), "hipMemsetD32Async") || // +inf
             !hip_ok(hipMemsetAsync(ctx->heavy, 0, L * sizeof(int32_t), st), "hipMemsetAsync") ||
             !hip_ok(hipMemsetAsync(ctx->drift_max, 0, sizeof(unsigned), st), "hipMemsetAsync") ||
-            !hip_ok(hipMemsetAsync(ctx->heavy_cnt, 0, sizeof(int32_t), st), "hipMemsetAsync")) {
+            !hip_ok(hipMemsetAsync(ctx->heavy_cnt, 0, sizeof(int32_t), st), "hipMemsetAsync") ||
+            !hip_ok(hipMemsetAsync(ctx->group_parts, 0, ctx->ngroups * sizeof(int32_t), st), "hipMemsetAsync")) {
             kmeans_destroy(ctx);
             return KM_ERR_HIP;
         }

@@ -71,6 +71,8 @@ struct AssignArgs {
     int tile;
     // candidate capacities in use (at most the LDS capacities)
     int sw_main, fr_main, sw_heavy, fr_heavy, heavy_m;
+    int32_t *group_parts; // [ngroups] parts each group is split into (0 or 1: whole), set from the last step
+    int split_sn;         // a group whose list reaches this length is split at the next step
     const int32_t *ctl; // device loop control: every kernel returns at once when ctl[CTL_STOP]
 };
 
@@ -144,6 +146,15 @@ struct BlockCombine {
     int done;
 };
 
+// Units of work of a main-pass workgroup (2D): (group, part, parts) entries
+// that its waves claim one after the other.
+constexpr int MAX_PARTS = 4;  // a group's leaves are split over at most this many waves
+constexpr int SPLIT_SN = 48;  // list length from which a group is split at the next step
+struct UnitList {
+    int32_t unit[G_WAVES * MAX_PARTS]; // group slot | part << 8 | parts << 16
+    int n, next;
+};
+
 __device__ inline void combine_init(BlockCombine &bc)
 {
     if (threadIdx.x < NSTAT)
@@ -153,8 +164,9 @@ __device__ inline void combine_init(BlockCombine &bc)
     __syncthreads();
 }
 
+// Adds one wave's counters to the workgroup's totals.
 template <class T>
-__device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const T (&c)[NSTAT], int64_t row)
+__device__ inline void combine_add(BlockCombine &bc, const T (&c)[NSTAT])
 {
     const int lane = lane_id();
     int64_t mine = 0;
@@ -164,6 +176,15 @@ __device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const 
             mine = c[q];
     if (lane < NSTAT && mine)
         __hip_atomic_fetch_add(&bc.v[lane], (unsigned long long)mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds one wave's counters (if any) and, in the last wave of the workgroup to
+// get here, writes the workgroup's row.
+template <class T>
+__device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const T (&c)[NSTAT], int64_t row)
+{
+    const int lane = lane_id();
+    combine_add(bc, c);
     int last = 0;
     if (lane == 0)
         last = __hip_atomic_fetch_add(&bc.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == G_WAVES - 1;
@@ -872,9 +893,11 @@ __device__ inline void defer_leaf(const AssignArgs &A, int64_t l, int32_t (&st)[
 // does not fit, or that has more than heavy_m candidates, goes to the
 // per-leaf pass.  Results are the same on every path.
 template <int D>
-__device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t (&st)[NSTAT])
+__device__ void group_work(int64_t g, int part, int parts, const AssignArgs &A, WaveMain &sh,
+                           int32_t (&st)[NSTAT])
 {
     const int lane = lane_id();
+    const bool inpart = (lane & (parts - 1)) == part; // this unit's leaves: t = part, part + parts, ...
     const float e = err_bound(A.cmax_bits);
     const TreeArgs *Tp = A.trees + A.group_cloud[g];
     const int64_t l0 = A.group_leaf[g];
@@ -902,15 +925,23 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
         r.ocb = A.cb_s[r.own];
         const float s = box_maxd<D>(r.lo, r.hi, r.oc);
         keep = inter_keep(r.ocb, s, e);
-        if (keep)
+        if (keep && inpart)
             A.leaf_r[l0 + lane] = dist_hi(s, e); // every point is within this of c_own
     }
     const uint64_t kept = __ballot(keep);
-    uint64_t todo = __ballot(lane < nl) & ~kept;
+    const uint64_t todo_all = __ballot(lane < nl) & ~kept;
+    uint64_t todo = todo_all & __ballot(inpart);
     if (kept)
-        st[ST_KEEP_LEAF_PTS] += wave_sum_i32(keep ? r.size : 0);
+        st[ST_KEEP_LEAF_PTS] += wave_sum_i32(keep && inpart ? r.size : 0);
+    // the unit holding the group's first leaf to decide sets the group's
+    // parts for the next step (from its first list)
+    const bool lead = todo_all ? (((todo_all & (~todo_all + 1ull)) & todo) != 0) : part == 0;
     if (!todo) {
-        st[ST_GROUP_SKIP] += 1;
+        if (!todo_all && part == 0) {
+            st[ST_GROUP_SKIP] += 1;
+            if (lane == 0 && parts > 1)
+                A.group_parts[g] = 1;
+        }
         return;
     }
     // The points of every leaf still to decide, loaded at once: one round
@@ -944,6 +975,17 @@ __device__ void group_work(int64_t g, const AssignArgs &A, WaveMain &sh, int32_t
         }
         const float Ru = -wave_min_f32(mine ? -r.R : 0.0f); // every point of the unit is within Ru of a centroid
         const int sn = wave_search<D>(ulo, uhi, Tp, e, sh, A.sw_main, A.fr_main, prune_threshold_r(Ru, e));
+        if (D == 2 && lead && !per_leaf && lane == 0) {
+            // a long list: the next step splits the group's leaves over 2 or 4
+            // waves (at most one per leaf to decide)
+            // (a part's list is shorter than the whole group's: a split group
+            // stays split down to a quarter of the threshold)
+            const int nd = __popcll(todo_all);
+            const int lim = parts > 1 ? (A.split_sn + 3) / 4 : A.split_sn;
+            const int want = sn < 0 || sn >= lim ? (nd >= 4 ? 4 : (nd >= 2 ? 2 : 1)) : 1;
+            if (want != (parts > 1 ? parts : 1))
+                A.group_parts[g] = want;
+        }
         if (sn < 0) {
             if (!per_leaf) {
                 st[ST_GROUP_OVF] += 1;
@@ -1018,13 +1060,56 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
         return; // the run is over (the whole workgroup returns)
     __shared__ WaveMain wsh[G_WAVES];
     __shared__ BlockCombine bc;
-    combine_init(bc);
+    if (D == 3) {
+        // one group per wave: the loop below costs the 3D kernel registers
+        // (3 waves per SIMD instead of 4), and 3D lists stay short
+        combine_init(bc);
+        const int wv = uniform_int(threadIdx.x / WAVE);
+        const int64_t g = (int64_t)blockIdx.x * G_WAVES + wv;
+        int32_t st[NSTAT] = {};
+        if (g < A.ngroups)
+            group_work<D>(g, 0, 1, A, wsh[wv], st);
+        combine_end(bc, A, st, blockIdx.x);
+        return;
+    }
+    __shared__ UnitList ul;
+    if (threadIdx.x == 0) {
+        // the workgroup's groups as units of work: a group split at this step
+        // (a long list at the last one) gives one unit per part
+        int n = 0;
+        for (int u = 0; u < G_WAVES; ++u) {
+            const int64_t g = (int64_t)blockIdx.x * G_WAVES + u;
+            if (g >= A.ngroups)
+                break;
+            const int gp = A.group_parts[g];
+            const int parts = gp >= 4 ? 4 : (gp >= 2 ? 2 : 1); // a power of two
+            for (int p = 0; p < parts; ++p)
+                ul.unit[n++] = u | (p << 8) | (parts << 16);
+        }
+        ul.n = n;
+        ul.next = 0;
+    }
+    combine_init(bc); // (its barrier also publishes the unit list)
     const int wv = uniform_int(threadIdx.x / WAVE); // the compiler then keeps group values in scalar registers
-    const int64_t g = (int64_t)blockIdx.x * G_WAVES + wv;
-    int32_t st[NSTAT] = {}; // one group's counts fit 32 bits (at most 512 points x 256 candidates)
-    if (g < A.ngroups) // whole wave; nothing in group_work synchronises across waves
-        group_work<D>(g, A, wsh[wv], st);
-    combine_end(bc, A, st, blockIdx.x);
+    // every wave claims units until none is left (a bounded loop: no wave
+    // waits for another, and nothing in group_work synchronises across waves);
+    // a unit's counters go to the workgroup's totals at once, so that none
+    // stays live from one unit to the next
+    while (true) {
+        int i = 0;
+        if (lane_id() == 0)
+            i = __hip_atomic_fetch_add(&ul.next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        i = uniform_int(rl_i(i, 0));
+        if (i >= ul.n)
+            break;
+        const int un = uniform_int(ul.unit[i]);
+        const int64_t g = (int64_t)blockIdx.x * G_WAVES + (un & 0xff);
+        int32_t st[NSTAT] = {}; // one group's counts fit 32 bits (at most 512 points x 256 candidates)
+        group_work<D>(g, (un >> 8) & 0xff, un >> 16, A, wsh[wv], st);
+        combine_add(bc, st);
+    }
+    const int32_t none[NSTAT] = {};
+    combine_end(bc, A, none, blockIdx.x);
 }
 
 // k_assign_heavy: the leaves k_assign_waves deferred (a list of
@@ -1432,13 +1517,16 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in)
         A.sw_heavy = 32;
         A.fr_heavy = 128;
         A.heavy_m = 2;
+        A.split_sn = 1; // every group with two leaves to decide is split from its second step
     } else {
         A.sw_main = SW_MAIN;
         A.fr_main = FR_MAIN;
         A.sw_heavy = SW_HEAVY;
         A.fr_heavy = FR_HEAVY;
         A.heavy_m = HEAVY_M;
+        A.split_sn = SPLIT_SN;
     }
+    A.group_parts = ctx->group_parts;
     return A;
 }
 

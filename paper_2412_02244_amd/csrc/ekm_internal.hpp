@@ -662,6 +662,7 @@ struct km_ctx {
     // groups: runs of at most GROUP_LEAVES consecutive leaves inside one group cell
     int64_t ngroups = 0;
     int32_t *group_leaf = nullptr; // [ngroups+1] first leaf of each group
+    int32_t *group_parts = nullptr; // [ngroups] parts the main pass splits each group into (0: whole)
     float4 *group_box = nullptr;  // [ngroups][2]
     // A5: exact sums
     int64_t *acc = nullptr;       // [k][d][2]
