@@ -68,8 +68,10 @@ typedef enum {
                              kmeans_phase_times); costs a few microseconds per step */
 #define KM_FLAG_SMALL_LISTS 4u /* testing aid: tiny candidate-list capacities, so that every
                                   fallback path (group overflow, deferred leaves, scan of all
-                                  k centroids) runs, and the per-step statistics folded by
-                                  many workgroups; results are unchanged, only slower */
+                                  k centroids) runs, the per-step statistics are folded by
+                                  many workgroups, and every 2D leaf group with two leaves
+                                  to decide is split over waves; results are unchanged,
+                                  only slower */
 #define KM_FLAG_CELL_LEAVES 8u /* indexed path: a leaf is the largest Morton cell holding at
                                   most f points (default: f consecutive points of a group
                                   cell, the largest Morton cell holding at most G * f points,

@@ -12,6 +12,13 @@
 // Morton-sorted run into equal consecutive pieces splits space along the
 // interleaved coordinates, i.e. kd-style splits, three levels at a time.
 // A wide tree keeps the descent short: three levels cover k = 4096.
+// The sort runs at every TREE_RESORT-th step; in between, the tree is
+// rebuilt over the order it had (any grouping of the centroids gives exact
+// boxes, a stale order only looser ones).
+//
+// Also here: the inter bound of Eq. (3) for every centroid (the distance to
+// its nearest other centroid), by a pair scan inside the small-k tree launch
+// or by a search of the large-k tree.
 #include "ekm_internal.hpp"
 
 namespace ekm {
