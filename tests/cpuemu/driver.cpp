@@ -1,7 +1,7 @@
 // Runs the emulated library on one input file and writes what it returns.
 //
 //   driver kmeans in.bin out.bin
-//     in:  int64 n, d, k, iters, algo, leaf_size, flags, point_dtype;
+//     in:  int64 n, d, k, iters, algo, leaf_size, flags | cand_tile << 20, point_dtype;
 //          points (n x d, FP32 or FP64 per point_dtype); c0 (k x d FP64)
 //     out: per step: assignment (n int32), centroids (k x d FP64),
 //          statistics (7 int64 + 1 double, the km_iter_stats layout)
@@ -70,9 +70,9 @@ int main(int argc, char **argv)
     cfg.algo = (int32_t)h[4];
     cfg.leaf_size = (int32_t)h[5];
     cfg.flags = (uint32_t)(h[6] & 0xffff);
+    cfg.cand_tile = (int32_t)((h[6] >> 20) & 0xfff); // (leaves per list; 0 = default)
     std::vector<int32_t> a(n);
     if (!strcmp(argv[1], "runb")) {
-        cfg.cand_tile = (int32_t)((h[6] >> 20) & 0xfff);
         cfg.flags = 0;
         int32_t tuned[2] = {0, 0};
         if (kmeans_run_batched(pts.data(), pt_offs.data(), c.data(), c_offs.data(), a.data(), (int32_t)B, &cfg,

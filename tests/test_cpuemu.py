@@ -183,6 +183,25 @@ def test_emulated_fallback_scan_with_fp32_blind_ties(driver, tmp_path):
     assert got[0][2]["rechecked"] > 0 and got[0][2]["fallback_points"] > 0, got[0][2]
 
 
+def test_emulated_long_candidate_lists(driver, tmp_path):
+    """2,000 uniform points and, far away, a tight blob of 150 points holding
+    all 150 centroids: from every uniform leaf the blob's centroids are
+    almost equidistant, so each leaf keeps them all as candidates (lists of
+    about 150, several 64-entry chunks per scan and recheck), one leaf per
+    group.  Four steps equal the oracle's."""
+    rng = np.random.default_rng(85)
+    blob = np.array([6.0, 6.0]) + rng.normal(0, 0.01, (150, 2))
+    x = np.concatenate([rng.uniform(0, 1, (2000, 2)), blob]).astype(np.float32)
+    c0 = x[2000:].astype(np.float64)
+    ref = oracle.lloyd(x, c0, max_iter=4)
+    got = _run(driver, tmp_path, "kmeans", x, c0, 4, KM_INDEXED, 0, KM_FLAG_SSE | (1 << 20))
+    for t, (a, c, st) in enumerate(got):
+        np.testing.assert_array_equal(a, ref["a_hist"][t], err_msg=f"step {t + 1}")
+        np.testing.assert_array_equal(c, ref["c_hist"][t], err_msg=f"step {t + 1}")
+        assert st["sse"] == pytest.approx(ref["sse"][t], rel=1e-12)
+    assert got[0][2]["cand_total"] > 100 * got[0][2]["leaves"] // 2, got[0][2]
+
+
 def test_emulated_long_trajectory_inter_bounds(driver, tmp_path):
     """Ten steps: the exact sums are carried from step to step and moved
     point by point or leaf by leaf, the inter bounds keep leaves and points,
