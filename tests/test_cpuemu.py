@@ -202,6 +202,25 @@ def test_emulated_long_candidate_lists(driver, tmp_path):
     assert got[0][2]["cand_total"] > 100 * got[0][2]["leaves"] // 2, got[0][2]
 
 
+def test_emulated_uniform_long_lists(driver, tmp_path):
+    """4,000 uniform points and 1,500 uniform centroids drawn apart from
+    them: at the first step the leaves span wide boxes against a dense
+    centroid set, with lists of 30 to 130 candidates that differ from leaf
+    to leaf (unlike the blob case above, where every leaf keeps the same
+    ones).  Three steps equal the oracle's."""
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 1, (4000, 2)).astype(np.float32)
+    c0 = rng.uniform(0, 1, (1500, 2))
+    ref = oracle.lloyd(x, c0, max_iter=3)
+    got = _run(driver, tmp_path, "kmeans", x, c0, 3, KM_INDEXED, 0, KM_FLAG_SSE | (1 << 20))
+    for t, (a, c, st) in enumerate(got):
+        np.testing.assert_array_equal(a, ref["a_hist"][t], err_msg=f"step {t + 1}")
+        np.testing.assert_array_equal(c, ref["c_hist"][t], err_msg=f"step {t + 1}")
+        assert st["sse"] == pytest.approx(ref["sse"][t], rel=1e-12)
+    st = got[0][2]
+    assert st["cand_total"] > 40 * st["leaves"], st  # long lists
+
+
 def test_emulated_long_trajectory_inter_bounds(driver, tmp_path):
     """Ten steps: the exact sums are carried from step to step and moved
     point by point or leaf by leaf, the inter bounds keep leaves and points,
