@@ -136,7 +136,8 @@ static WsParts ws_parts(const km_config *cfg, const WsCounts &c)
                   al(c.pair_blocks * PAIR_WAVES, sizeof(PairItem)) +
                   3 * al(L, 4) + al(1, 4) + 3 * al(k, 4) + al(1, 4) + al(k * d, 8);
     p.rest += al(CTL_N, 4);
-    const int64_t nblk = indexed ? (c.groups + 3) / 4 + heavy_blocks(c.kmax) : (n + 255) / 256;
+    const int64_t nblk = indexed ? (c.groups + main_waves(d) - 1) / main_waves(d) + heavy_blocks(c.kmax)
+                                 : (n + 255) / 256;
     if (leaf_state)
         p.groups = al(c.groups + 1, 4) + al(2 * c.groups, 16) + 2 * al(c.groups, 4);
     p.groups += al(nblk * NSTAT, 8);

@@ -25,7 +25,7 @@
 namespace ekm {
 
 constexpr int ASSIGN_THREADS = 256;
-constexpr int G_WAVES = ASSIGN_THREADS / WAVE; // independent waves per workgroup
+constexpr int G_WAVES = ASSIGN_THREADS / WAVE; // waves per workgroup of the per-leaf pass
 // Per-wave LDS capacities: candidate list entries and descent entries per
 // level.  A leaf whose list does not fit in the main pass goes to the
 // per-leaf pass, whose waves have room for crowded leaves (one workgroup
@@ -151,7 +151,7 @@ struct BlockCombine {
 constexpr int MAX_PARTS = 4;  // a group's leaves are split over at most this many waves
 constexpr int SPLIT_SN = 48;  // list length from which a group is split at the next step
 struct UnitList {
-    int32_t unit[G_WAVES * MAX_PARTS]; // group slot | part << 8 | parts << 16
+    int32_t unit[MAIN_WAVES<2> * MAX_PARTS]; // group slot | part << 8 | parts << 16
     int n, next;
 };
 
@@ -187,7 +187,8 @@ __device__ inline void combine_end(BlockCombine &bc, const AssignArgs &A, const 
     combine_add(bc, c);
     int last = 0;
     if (lane == 0)
-        last = __hip_atomic_fetch_add(&bc.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == G_WAVES - 1;
+        last = __hip_atomic_fetch_add(&bc.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+               (int)(blockDim.x / WAVE) - 1;
     if (!rl_i(last, 0))
         return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -1054,18 +1055,19 @@ __device__ void group_work(int64_t g, int part, int parts, const AssignArgs &A, 
 }
 
 template <int D>
-__global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
+__global__ void __launch_bounds__(MAIN_WAVES<D> * WAVE) k_assign_waves(AssignArgs A)
 {
+    constexpr int NW = MAIN_WAVES<D>;
     if (A.ctl[CTL_STOP])
         return; // the run is over (the whole workgroup returns)
-    __shared__ WaveMain wsh[G_WAVES];
+    __shared__ WaveMain wsh[NW];
     __shared__ BlockCombine bc;
     if (D == 3) {
         // one group per wave: the loop below costs the 3D kernel registers
         // (3 waves per SIMD instead of 4), and 3D lists stay short
         combine_init(bc);
         const int wv = uniform_int(threadIdx.x / WAVE);
-        const int64_t g = (int64_t)blockIdx.x * G_WAVES + wv;
+        const int64_t g = (int64_t)blockIdx.x * NW + wv;
         int32_t st[NSTAT] = {};
         if (g < A.ngroups)
             group_work<D>(g, 0, 1, A, wsh[wv], st);
@@ -1077,8 +1079,8 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
         // the workgroup's groups as units of work: a group split at this step
         // (a long list at the last one) gives one unit per part
         int n = 0;
-        for (int u = 0; u < G_WAVES; ++u) {
-            const int64_t g = (int64_t)blockIdx.x * G_WAVES + u;
+        for (int u = 0; u < NW; ++u) {
+            const int64_t g = (int64_t)blockIdx.x * NW + u;
             if (g >= A.ngroups)
                 break;
             const int gp = A.group_parts[g];
@@ -1103,7 +1105,7 @@ __global__ void __launch_bounds__(ASSIGN_THREADS) k_assign_waves(AssignArgs A)
         if (i >= ul.n)
             break;
         const int un = uniform_int(ul.unit[i]);
-        const int64_t g = (int64_t)blockIdx.x * G_WAVES + (un & 0xff);
+        const int64_t g = (int64_t)blockIdx.x * NW + (un & 0xff);
         int32_t st[NSTAT] = {}; // one group's counts fit 32 bits (at most 512 points x 256 candidates)
         group_work<D>(g, (un >> 8) & 0xff, un >> 16, A, wsh[wv], st);
         combine_add(bc, st);
@@ -1531,7 +1533,11 @@ static AssignArgs make_args(km_ctx *ctx, const double *c_in)
 }
 
 // Workgroups of the indexed main pass (one wave per group).
-int64_t assign_grid(km_ctx *ctx) { return (ctx->ngroups + G_WAVES - 1) / G_WAVES; }
+int64_t assign_grid(km_ctx *ctx)
+{
+    const int w = main_waves(ctx->d);
+    return (ctx->ngroups + w - 1) / w;
+}
 
 // Rows of per-block (brute) or per-workgroup (indexed) statistics partials.
 int64_t assign_blocks(km_ctx *ctx)
@@ -1553,9 +1559,9 @@ km_status run_assign(km_ctx *ctx, const double *c_in, hipEvent_t between)
     if (ctx->cfg.algo == KM_INDEXED) {
         const unsigned nhw = (unsigned)ctx->heavy_wgs;
         if (D == 2)
-            hipLaunchKernelGGL(k_assign_waves<2>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
+            hipLaunchKernelGGL(k_assign_waves<2>, dim3(nwg), dim3(MAIN_WAVES<2> * WAVE), 0, st, A);
         else
-            hipLaunchKernelGGL(k_assign_waves<3>, dim3(nwg), dim3(ASSIGN_THREADS), 0, st, A);
+            hipLaunchKernelGGL(k_assign_waves<3>, dim3(nwg), dim3(MAIN_WAVES<3> * WAVE), 0, st, A);
         if (between)
             hipEventRecord(between, st);
         if (D == 2)

@@ -30,6 +30,12 @@ constexpr int HEAVY_M = 256;
 // then every CU takes part; otherwise a quarter of them, which keeps the
 // usually empty pass short.
 inline int heavy_blocks(int64_t kmax) { return kmax >= 8192 ? 256 : 64; }
+// Waves per workgroup of the indexed main pass (one group per wave; in 2D the
+// waves claim units of work from a shared list, and 8 of them balance long
+// units better than 4; the 3D kernel keeps 4, its registers allow no more).
+template <int D>
+constexpr int MAIN_WAVES = D == 2 ? 8 : 4;
+inline int main_waves(int d) { return d == 2 ? MAIN_WAVES<2> : MAIN_WAVES<3>; }
 constexpr int TREE_BUCKET = 8;   // centroids per centroid-tree leaf bucket
 constexpr int TREE_MAX_LEVELS = 8;
 constexpr int TREE_START_MAX = 512; // nodes a descent evaluates at its first level
