@@ -295,7 +295,10 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
         return;
     }
     const int have_prev = uniform_int(ctl[CTL_STEPS] > 0 ? 1 : 0);
-    const TreeArgs &T = trees[blockIdx.x];
+    // the cloud's tree layout, loaded once into (scalar) registers: the
+    // phases below read it after barriers, where a load from memory would
+    // cost a round trip each time
+    const TreeArgs T = trees[blockIdx.x];
     const Grid g = grids[blockIdx.x];
     const int64_t c0 = T.c0, k = T.k;
     const double *c = c_all + c0 * D;
@@ -431,23 +434,36 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
     for (int b = tid; b < nb0; b += TREE_THREADS) {
         float4 lo, hi;
         box_empty(lo, hi);
-        const int te = (b + 1) * TREE_BUCKET < kk ? (b + 1) * TREE_BUCKET : kk;
-        for (int t = b * TREE_BUCKET; t < te; ++t)
-            box_add(lo, hi, cq[id[t]]);
+        const int tl = ((b + 1) * TREE_BUCKET < kk ? (b + 1) * TREE_BUCKET : kk) - 1; // the bucket's last
+        // all loads at once: indices past the bucket's end repeat its last
+        // centroid, which leaves the box unchanged
+        uint32_t ids[TREE_BUCKET];
+#pragma unroll
+        for (int u = 0; u < TREE_BUCKET; ++u)
+            ids[u] = id[b * TREE_BUCKET + u < tl ? b * TREE_BUCKET + u : tl];
+#pragma unroll
+        for (int u = 0; u < TREE_BUCKET; ++u)
+            box_add(lo, hi, cq[ids[u]]);
         nlo[b] = lo;
         nhi[b] = hi;
         T.node_lo[b] = lo;
         T.node_hi[b] = hi;
     }
     __syncthreads();
-    for (int l = 1; l < T.nlev; ++l) {
+#pragma unroll // constant level indices: the layout stays in registers
+    for (int l = 1; l < TREE_MAX_LEVELS; ++l) {
+        if (l >= T.nlev)
+            break;
         const int off = (int)T.lev_off[l], poff = (int)T.lev_off[l - 1], psz = (int)T.lev_size[l - 1];
         for (int i = tid; i < (int)T.lev_size[l]; i += TREE_THREADS) {
             float4 lo, hi;
             box_empty(lo, hi);
-            const int ce = 8 * i + 8 < psz ? 8 * i + 8 : psz;
-            for (int ch = 8 * i; ch < ce; ++ch)
+            const int cl = (8 * i + 8 < psz ? 8 * i + 8 : psz) - 1; // the node's last child
+#pragma unroll // all loads at once: a repeated last child leaves the box unchanged
+            for (int u = 0; u < 8; ++u) {
+                const int ch = 8 * i + u < cl ? 8 * i + u : cl;
                 box_union(lo, hi, nlo[poff + ch], nhi[poff + ch]);
+            }
             nlo[off + i] = lo;
             nhi[off + i] = hi;
             T.node_lo[off + i] = lo;
