@@ -279,9 +279,11 @@ int64_t pair_plan(const int64_t *c_off, int B, std::vector<PairItem> *items)
 // cloud and global ids in cs[].w.  The workgroups after those run the pair
 // scan of the inter bound (pair_block), which reads only the FP64 centroids,
 // so both run side by side in one launch.
+// At most 64 VGPRs (8 waves per SIMD): two tree workgroups per CU when a
+// launch covers many clouds.
 static_assert(TREE_WAVES == PAIR_WAVES, "a pair-scan workgroup is a tree workgroup");
 template <int D>
-__global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all, const TreeArgs *trees,
+__global__ void __launch_bounds__(TREE_THREADS, 8) k_tree_small(const double *c_all, const TreeArgs *trees,
                                                              const Grid *grids, float4 *c32, unsigned *cmax_bits,
                                                              unsigned *cb_s, double *c_prev_all, unsigned *drift_max,
                                                              const PairItem *pairs, int nclouds, int kcap,
@@ -295,12 +297,20 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
         return;
     }
     const int have_prev = uniform_int(ctl[CTL_STEPS] > 0 ? 1 : 0);
-    // the cloud's tree layout, loaded once into (scalar) registers: the
-    // phases below read it after barriers, where a load from memory would
-    // cost a round trip each time
-    const TreeArgs T = trees[blockIdx.x];
+    // the cloud's tree layout, read once into (scalar) registers: the
+    // phases below use it after barriers, where a read through T would be
+    // a memory round trip each time
+    const TreeArgs &T = trees[blockIdx.x];
     const Grid g = grids[blockIdx.x];
     const int64_t c0 = T.c0, k = T.k;
+    float4 *const cs = T.cs, *const node_lo = T.node_lo, *const node_hi = T.node_hi;
+    const int nnodes = uniform_int((int)T.nnodes), nlev = uniform_int(T.nlev);
+    int lev_off[TREE_MAX_LEVELS], lev_size[TREE_MAX_LEVELS];
+#pragma unroll
+    for (int l = 0; l < TREE_MAX_LEVELS; ++l) {
+        lev_off[l] = uniform_int(l < nlev ? (int)T.lev_off[l] : 0);
+        lev_size[l] = uniform_int(l < nlev ? (int)T.lev_size[l] : 0);
+    }
     const double *c = c_all + c0 * D;
     const int resort = uniform_int(ctl[CTL_STEPS] % TREE_RESORT == 0 ? 1 : 0);
     // kcap: the largest cloud of the launch, rounded up (small_tree_lds)
@@ -332,7 +342,7 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
         c32[c0 + j] = q4;
         key[j] = kb >> shift;
         // the order to keep: tree position j held centroid T.cs[j].w (a global id)
-        id[j] = resort ? (uint32_t)j : (uint32_t)(__float_as_int(T.cs[j].w) - (int)c0);
+        id[j] = resort ? (uint32_t)j : (uint32_t)(__float_as_int(cs[j].w) - (int)c0);
     }
     nb = -wave_min_f32(-nb);
     dm = -wave_min_f32(-dm);
@@ -423,51 +433,70 @@ __global__ void __launch_bounds__(TREE_THREADS) k_tree_small(const double *c_all
     __syncthreads();
     // sorted ids are back in `id`; node boxes go to LDS (over key2/id2,
     // free now: room for kcap / 4 float4, see small_tree_lds) and out
-    float4 *nlo = (float4 *)key2, *nhi = nlo + T.nnodes;
+    float4 *nlo = (float4 *)key2, *nhi = nlo + nnodes;
     for (int t = tid; t < kk; t += TREE_THREADS) {
         int cid = (int)id[t];
         float4 p = cq[cid];
         p.w = __int_as_float((int)c0 + cid);
-        T.cs[t] = p;
+        cs[t] = p;
     }
-    const int nb0 = (int)T.lev_size[0];
+    const int nb0 = lev_size[0];
     for (int b = tid; b < nb0; b += TREE_THREADS) {
         float4 lo, hi;
         box_empty(lo, hi);
         const int tl = ((b + 1) * TREE_BUCKET < kk ? (b + 1) * TREE_BUCKET : kk) - 1; // the bucket's last
         // all loads at once: indices past the bucket's end repeat its last
         // centroid, which leaves the box unchanged
+        // (the centroids in two batches of 4: fewer registers, so that two
+        // tree workgroups still fit a CU when many clouds are launched)
         uint32_t ids[TREE_BUCKET];
 #pragma unroll
         for (int u = 0; u < TREE_BUCKET; ++u)
             ids[u] = id[b * TREE_BUCKET + u < tl ? b * TREE_BUCKET + u : tl];
 #pragma unroll
-        for (int u = 0; u < TREE_BUCKET; ++u)
-            box_add(lo, hi, cq[ids[u]]);
+        for (int h = 0; h < TREE_BUCKET; h += 4) {
+            float4 p[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                p[u] = cq[ids[h + u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                box_add(lo, hi, p[u]);
+        }
         nlo[b] = lo;
         nhi[b] = hi;
-        T.node_lo[b] = lo;
-        T.node_hi[b] = hi;
+        node_lo[b] = lo;
+        node_hi[b] = hi;
     }
     __syncthreads();
 #pragma unroll // constant level indices: the layout stays in registers
     for (int l = 1; l < TREE_MAX_LEVELS; ++l) {
-        if (l >= T.nlev)
+        if (l >= nlev)
             break;
-        const int off = (int)T.lev_off[l], poff = (int)T.lev_off[l - 1], psz = (int)T.lev_size[l - 1];
-        for (int i = tid; i < (int)T.lev_size[l]; i += TREE_THREADS) {
+        const int off = lev_off[l], poff = lev_off[l - 1], psz = lev_size[l - 1];
+        for (int i = tid; i < lev_size[l]; i += TREE_THREADS) {
             float4 lo, hi;
             box_empty(lo, hi);
             const int cl = (8 * i + 8 < psz ? 8 * i + 8 : psz) - 1; // the node's last child
-#pragma unroll // all loads at once: a repeated last child leaves the box unchanged
-            for (int u = 0; u < 8; ++u) {
-                const int ch = 8 * i + u < cl ? 8 * i + u : cl;
-                box_union(lo, hi, nlo[poff + ch], nhi[poff + ch]);
+            // two batches of 4 children, each batch's loads at once (a
+            // repeated last child leaves the box unchanged)
+#pragma unroll
+            for (int h = 0; h < 8; h += 4) {
+                float4 clo[4], chi[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ch = 8 * i + h + u < cl ? 8 * i + h + u : cl;
+                    clo[u] = nlo[poff + ch];
+                    chi[u] = nhi[poff + ch];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    box_union(lo, hi, clo[u], chi[u]);
             }
             nlo[off + i] = lo;
             nhi[off + i] = hi;
-            T.node_lo[off + i] = lo;
-            T.node_hi[off + i] = hi;
+            node_lo[off + i] = lo;
+            node_hi[off + i] = hi;
         }
         __syncthreads();
     }
