@@ -756,6 +756,42 @@ __global__ void __launch_bounds__(256) k_tree_level(TreeArgs T, int l)
     T.node_hi[off + i] = hi;
 }
 
+// Every level from l0 up, in one workgroup: level l0 - 1 (at most
+// TREE_UPPER_CAP nodes) is read once into LDS, and each level above is
+// built there from its children and written out (one launch instead of
+// one per level; the levels are stored one after the other, level 0 first).
+constexpr int TREE_UPPER_CAP = 2048, TREE_UPPER_SPAN = 2560, TREE_UPPER_THREADS = 1024;
+// the nodes from level l0 - 1 up: P <= TREE_UPPER_CAP, then at most
+// ceil(P / 8) + ceil(P / 64) + ... <= P / 7 + one per level
+static_assert(TREE_UPPER_SPAN >= TREE_UPPER_CAP + TREE_UPPER_CAP / 7 + TREE_MAX_LEVELS, "the levels fit the LDS");
+__global__ void __launch_bounds__(TREE_UPPER_THREADS) k_tree_upper(TreeArgs T, int l0)
+{
+    __shared__ float4 blo[TREE_UPPER_SPAN], bhi[TREE_UPPER_SPAN];
+    const int tid = threadIdx.x;
+    const int64_t base = T.lev_off[l0 - 1];
+    const int P = (int)T.lev_size[l0 - 1];
+    for (int i = tid; i < P; i += TREE_UPPER_THREADS) {
+        blo[i] = T.node_lo[base + i];
+        bhi[i] = T.node_hi[base + i];
+    }
+    __syncthreads();
+    for (int l = l0; l < T.nlev; ++l) {
+        const int off = (int)(T.lev_off[l] - base), poff = (int)(T.lev_off[l - 1] - base);
+        const int psz = (int)T.lev_size[l - 1], n = (int)T.lev_size[l];
+        for (int i = tid; i < n; i += TREE_UPPER_THREADS) {
+            float4 lo, hi;
+            box_empty(lo, hi);
+            for (int ch = 8 * i; ch < 8 * i + 8 && ch < psz; ++ch)
+                box_union(lo, hi, blo[poff + ch], bhi[poff + ch]);
+            blo[off + i] = lo;
+            bhi[off + i] = hi;
+            T.node_lo[base + off + i] = lo;
+            T.node_hi[base + off + i] = hi;
+        }
+        __syncthreads();
+    }
+}
+
 // LDS of the small-k tree launch for clouds of at most kcap centroids (a
 // multiple of 64): fl32 copies, two key/id buffers, the per-wave digit
 // counts and the digit bases.  The pair-scan workgroups use its first
@@ -843,8 +879,12 @@ km_status build_centroid_tree(km_ctx *ctx, const double *c_in, bool resort)
     const TreeArgs &T = ctx->tree;
     hipLaunchKernelGGL(k_tree_buckets, dim3((unsigned)((T.lev_size[0] + 255) / 256)), dim3(256), 0, st, ctx->c32,
                        sid, k, T, hp);
-    for (int l = 1; l < T.nlev; ++l)
+    // levels over large ones, one launch each; then every level above in one
+    int l = 1;
+    for (; l < T.nlev && T.lev_size[l - 1] > TREE_UPPER_CAP; ++l)
         hipLaunchKernelGGL(k_tree_level, dim3((unsigned)((T.lev_size[l] + 255) / 256)), dim3(256), 0, st, T, l);
+    if (l < T.nlev)
+        hipLaunchKernelGGL(k_tree_upper, dim3(1), dim3(TREE_UPPER_THREADS), 0, st, T, l);
     const unsigned gnn = (unsigned)((k + NN_WAVES * NN_GROUP - 1) / (NN_WAVES * NN_GROUP));
     if (ctx->d == 2)
         hipLaunchKernelGGL(k_centroid_nn<2>, dim3(gnn), dim3(NN_WAVES * WAVE), 0, st, T, k, (const unsigned *)cmax,
