@@ -731,12 +731,28 @@ __global__ void __launch_bounds__(256) k_tree_buckets(const float4 *c32, const i
         return;
     float4 lo, hi;
     box_empty(lo, hi);
-    for (int64_t t = b * TREE_BUCKET; t < k && t < (b + 1) * TREE_BUCKET; ++t) {
-        const int id = sorted_id ? sorted_id[t] : __float_as_int(T.cs[t].w);
-        float4 p = c32[id];
-        box_add(lo, hi, p);
-        p.w = __int_as_float(id);
-        T.cs[t] = p;
+    // the bucket's ids, then its centroids, each batch of loads issued at
+    // once (the stores below would otherwise order every load after them);
+    // positions past the bucket's end repeat its last centroid, which
+    // leaves the box unchanged, and are not written
+    const int64_t t0 = b * TREE_BUCKET, tl = ((b + 1) * TREE_BUCKET < k ? (b + 1) * TREE_BUCKET : k) - 1;
+    int ids[TREE_BUCKET];
+#pragma unroll
+    for (int u = 0; u < TREE_BUCKET; ++u) {
+        const int64_t t = t0 + u < tl ? t0 + u : tl;
+        ids[u] = sorted_id ? sorted_id[t] : __float_as_int(T.cs[t].w);
+    }
+    float4 p[TREE_BUCKET];
+#pragma unroll
+    for (int u = 0; u < TREE_BUCKET; ++u)
+        p[u] = c32[ids[u]];
+#pragma unroll
+    for (int u = 0; u < TREE_BUCKET; ++u) {
+        box_add(lo, hi, p[u]);
+        if (t0 + u <= tl) {
+            p[u].w = __int_as_float(ids[u]);
+            T.cs[t0 + u] = p[u];
+        }
     }
     T.node_lo[b] = lo;
     T.node_hi[b] = hi;
