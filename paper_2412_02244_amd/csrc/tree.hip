@@ -531,13 +531,26 @@ __global__ void __launch_bounds__(256) k_centroid_prep(const double *c, int64_t 
                 c_prev[j * D + i] = c[j * D + i];
         }
     }
-    // non-negative floats order like their bit patterns
-    float m = -wave_min_f32(-nb);
-    float dm = -wave_min_f32(-dj);
+    // non-negative floats order like their bit patterns; the workgroup's
+    // maxima first, then one atomic per word and workgroup (atomics on one
+    // word from every wave serialise)
+    __shared__ float wm[256 / WAVE], wd[256 / WAVE];
+    const float m = -wave_min_f32(-nb);
+    const float dm = -wave_min_f32(-dj);
     if (lane_id() == 0) {
-        atomicMax(cmax_bits, __float_as_uint(m));
+        wm[threadIdx.x / WAVE] = m;
+        wd[threadIdx.x / WAVE] = dm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float bm = wm[0], bd = wd[0];
+        for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) {
+            bm = fmaxf(bm, wm[w]);
+            bd = fmaxf(bd, wd[w]);
+        }
+        atomicMax(cmax_bits, __float_as_uint(bm));
         if (c_prev)
-            atomicMax(drift_max, __float_as_uint(dm));
+            atomicMax(drift_max, __float_as_uint(bd));
     }
 }
 
