@@ -101,8 +101,35 @@ __global__ void __launch_bounds__(256) k_scan_points(const T *x, const int64_t *
         emsb = max(emsb, __shfl_xor(emsb, o));
         anynz |= __shfl_xor(anynz, o);
     }
-    if (lane_id() != 0)
+    // then the workgroup's result, published by one thread (atomics on the
+    // same words from every wave serialise)
+    constexpr int NW = 256 / WAVE;
+    __shared__ float slo[NW][D], shi[NW][D];
+    __shared__ int sflag[NW][4];
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        for (int i = 0; i < D; ++i) {
+            slo[wv][i] = lo[i];
+            shi[wv][i] = hi[i];
+        }
+        sflag[wv][0] = nonfin;
+        sflag[wv][1] = nelsb;
+        sflag[wv][2] = emsb;
+        sflag[wv][3] = anynz;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0)
         return;
+    for (int w = 1; w < NW; ++w) {
+        for (int i = 0; i < D; ++i) {
+            lo[i] = fminf(lo[i], slo[w][i]);
+            hi[i] = fmaxf(hi[i], shi[w][i]);
+        }
+        nonfin |= sflag[w][0];
+        nelsb = max(nelsb, sflag[w][1]);
+        emsb = max(emsb, sflag[w][2]);
+        anynz |= sflag[w][3];
+    }
     for (int i = 0; i < D; ++i) {
         atomicMin(&out->lo[i], ord_of(lo[i]));
         atomicMax(&out->hi[i], ord_of(hi[i]));
